@@ -1,0 +1,186 @@
+"""CPU oracle for exact two-terminal reliability (BAT + PLSA + Eq. 1).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The HIP
+library never imports, links or calls it, and shares no code with it.
+
+``bat_oracle.c`` holds the arithmetic (see its header for the paper passages
+it follows); this module is a ctypes wrapper around it plus the build step.
+``pbat.py`` runs the oracle over the equal divisions of Section 4 on several
+host processes; ``frontier_dp.py`` is a second, independent exact method
+(a frontier dynamic programme) used to pin full-size results.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bat_oracle.c")
+_LIB = os.path.join(_HERE, "libbat_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+ORC_OK = 0
+ORC_EINVAL = -1
+ORC_ETOOBIG = -2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, single thread)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build(force=False)
+            lib = ctypes.CDLL(_LIB)
+            i32, u64, i64 = ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64
+            P = ctypes.c_void_p
+            lib.orc_validate.argtypes = [i32, i32, P, P, i32, i32]
+            lib.orc_validate.restype = ctypes.c_int
+            lib.orc_dec_inv.argtypes = [i32, u64, P]
+            lib.orc_dec_inv.restype = None
+            lib.orc_dec.argtypes = [i32, P]
+            lib.orc_dec.restype = u64
+            lib.orc_bat_next.argtypes = [i32, P]
+            lib.orc_bat_next.restype = ctypes.c_int
+            lib.orc_plsa.argtypes = [i32, i32, P, P, i32, i32, i32, P, P, P]
+            lib.orc_plsa.restype = ctypes.c_int
+            lib.orc_pr.argtypes = [i32, P, P]
+            lib.orc_pr.restype = ctypes.c_double
+            lib.orc_range.argtypes = [i32, i32, P, P, i32, i32, i32, u64, u64, P, P, P, P, P, P]
+            lib.orc_range.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _arcs(arcs) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(arcs, dtype=np.int32).reshape(-1, 2))
+    return a
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle error {code}")
+        self.code = code
+
+
+@dataclass
+class RangeResult:
+    sum: float          # compensated pair collapsed: sum + comp
+    sum_hi: float
+    sum_lo: float
+    count: int
+    U: float            # mass of disconnected vectors (sum + comp)
+    T1: Optional[np.ndarray]
+    T0: Optional[np.ndarray]
+    layers: int
+    inspections: int
+
+    @property
+    def grad(self) -> Optional[np.ndarray]:
+        return None if self.T1 is None else self.T1 - self.T0
+
+
+def validate(n, arcs, p, s, t) -> int:
+    a = _arcs(arcs)
+    pv = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+    return _load().orc_validate(n, a.shape[0], _ptr(a), _ptr(pv), s, t)
+
+
+def dec_inv(m: int, c: int) -> tuple:
+    """Eq. 3: the 0-based c-th vector of the backward BAT (paper index c+1)."""
+    x = np.zeros(max(m, 1), dtype=np.uint8)
+    _load().orc_dec_inv(m, c, _ptr(x))
+    return tuple(int(v) for v in x[:m])
+
+
+def dec(x) -> int:
+    """Eq. 2: Dec(X) (0-based; the paper's index is Dec(X) + 1)."""
+    xa = np.ascontiguousarray(np.asarray(x, dtype=np.uint8))
+    return int(_load().orc_dec(len(xa), _ptr(xa)))
+
+
+def bat_sequence(m: int):
+    """All 2^m vectors in the order the BAT of Section 3.1 generates them."""
+    lib = _load()
+    x = np.zeros(max(m, 1), dtype=np.uint8)
+    out = [tuple(int(v) for v in x[:m])]
+    while lib.orc_bat_next(m, _ptr(x)):
+        out.append(tuple(int(v) for v in x[:m]))
+    return out
+
+
+def plsa(n, arcs, s, t, x, directed=False):
+    """PLSA on G(X): (connected, number of layers, layer index per node)."""
+    a = _arcs(arcs)
+    xa = np.ascontiguousarray(np.asarray(x, dtype=np.uint8))
+    assert xa.shape[0] == a.shape[0]
+    L = ctypes.c_int32(0)
+    I = ctypes.c_int64(0)
+    lay = np.zeros(n, dtype=np.int32)
+    rc = _load().orc_plsa(n, a.shape[0], _ptr(a), _ptr(xa), s, t, int(directed),
+                          ctypes.byref(L), ctypes.byref(I), _ptr(lay))
+    if rc < 0:
+        raise OracleError(rc)
+    return bool(rc), int(L.value), lay
+
+
+def pr(p, x) -> float:
+    pv = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+    xa = np.ascontiguousarray(np.asarray(x, dtype=np.uint8))
+    return float(_load().orc_pr(len(pv), _ptr(pv), _ptr(xa)))
+
+
+def reliability_range(n, arcs, p, s, t, c_lo, c_hi, grad=False, directed=False) -> RangeResult:
+    """BAT over backward-order indices [c_lo, c_hi)."""
+    a = _arcs(arcs)
+    m = a.shape[0]
+    pv = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+    if pv.shape[0] != m:
+        raise OracleError(ORC_EINVAL)
+    sum2 = np.zeros(2)
+    usum2 = np.zeros(2)
+    cnt = ctypes.c_uint64(0)
+    stats = np.zeros(2, dtype=np.int64)
+    T1 = np.zeros(2 * max(m, 1)) if grad else None
+    T0 = np.zeros(2 * max(m, 1)) if grad else None
+    rc = _load().orc_range(n, m, _ptr(a), _ptr(pv), s, t, int(directed), int(c_lo), int(c_hi),
+                           _ptr(sum2), ctypes.byref(cnt), _ptr(usum2), _ptr(T1), _ptr(T0), _ptr(stats))
+    if rc != ORC_OK:
+        raise OracleError(rc)
+    t1 = t0 = None
+    if grad:
+        t1 = T1[0:2 * m:2] + T1[1:2 * m:2]
+        t0 = T0[0:2 * m:2] + T0[1:2 * m:2]
+    return RangeResult(float(sum2[0] + sum2[1]), float(sum2[0]), float(sum2[1]), int(cnt.value),
+                       float(usum2[0] + usum2[1]), t1, t0, int(stats[0]), int(stats[1]))
+
+
+def reliability(n, arcs, p, s, t, grad=False, directed=False) -> RangeResult:
+    m = len(np.asarray(arcs).reshape(-1, 2))
+    return reliability_range(n, arcs, p, s, t, 0, 1 << m, grad=grad, directed=directed)
+
+
+def net_reliability(net, p=None, grad=False, directed=False) -> RangeResult:
+    """Convenience wrapper taking a ``bat_workloads.Network``."""
+    return reliability(net.n, net.arc_array(), net.p if p is None else p, net.s, net.t,
+                       grad=grad, directed=directed)
