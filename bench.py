@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark: exact two-terminal reliability of the 5x5 grid (m = 40).
+
+One "step" is one complete pass of the hot path over the headline workload:
+all 2^40 arc-state vectors of the 5x5 grid enumerated in BAT order, the s-t
+connectivity of each decided, and Pr(X) summed in FP64 over the connected
+ones, giving the exact R and the feasible-vector count.  The probabilities
+are resident in device memory before the timed region starts; R and the
+count stay in device memory (stream-ordered entry point).
+
+Printed (one JSON line): vectors/s as the metric value, plus time-to-exact-R
+(cold and warm, host call to R on the host), the forward+gradient vs forward
+time ratio on the 36-arc differentiation workload, the roofline of the
+enumeration kernel (HIP events on its own stream) and the CPU oracle's rate
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs, 64 lanes each, 2.4 GHz peak engine clock; one int32
+# lane-op per lane per clock on the vector ALUs.  A bit-sliced lane-op
+# handles 32 state vectors, so the bit-operation peak is 32x the lane rate.
+CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
+PEAK_LANE_OPS = CUS * LANES * CLOCK_HZ            # 3.93e13 int32 lane-ops/s
+PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 1.26e15 bit-ops/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the fwd+grad / batched comparisons")
+    ap.add_argument("--cpu-sample-log2", type=int, default=30,
+                    help="log2 of the state vectors in the oracle's timed sample")
+    ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    return ap.parse_args()
+
+
+def cpu_baseline(net, sample_log2: int):
+    """The CPU oracle (PBAT equal divisions over the host cores) on an evenly
+    spread sample of Eq. 6 divisions of the same workload."""
+    from oracle import pbat
+    procs = int(os.environ.get("BAT_BENCH_CPU_PROCS", "0")) or min(os.cpu_count() or 1, 16)
+    chi = 1 << 17                                  # divisions of 2^23 vectors at m = 40
+    mu_log2 = net.m - 17
+    k = max(1, 1 << max(0, sample_log2 - mu_log2))
+    divs = pbat.spread_divisions(chi, k)
+    r = pbat.run(net.n, net.arcs, net.p, net.s, net.t, chi, divisions=divs, processes=procs)
+    return {
+        "value": r.vectors / r.wall_s / 1e9,
+        "unit": "Gvec/s",
+        "cores": r.processes,
+        "kind": "oracle",
+        "sample": f"{len(divs)} of {chi} equal divisions (Eq. 6) spread evenly over the 2^{net.m} "
+                  f"counter, {r.vectors} vectors, {r.wall_s:.1f} s wall on {r.processes} processes",
+        "inspections_per_vector": r.inspections / r.vectors,
+        "layers_per_vector": r.layers / r.vectors,
+        "projected_time_to_R_s": (1 << net.m) / (r.vectors / r.wall_s),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the enumeration would shard "
+              f"by counter ranges across GPUs, which this build does not launch.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import bat_workloads as W
+    import paper_2209_09711_amd as B
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    net = W.config2()
+    m = net.m
+    nvec = 1 << m
+    arcs = net.arc_array()
+
+    # cold time-to-R: host call -> R on the host, first call (compiles the
+    # graph-specialised kernel)
+    t0 = time.perf_counter()
+    R_cold, cnt_cold = B.bat_reliability(net.n, arcs, net.p, net.s, net.t)
+    cold_s = time.perf_counter() - t0
+    info = B.bat_last_launch()
+    jit_ms = info.jit_ms
+
+    p_dev = torch.tensor(net.p, dtype=torch.float64, device=dev)
+    R_dev = torch.zeros((), dtype=torch.float64, device=dev)
+    c_dev = torch.zeros((), dtype=torch.int64, device=dev)
+    st_dev = torch.zeros((), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def step():
+        B.bat_reliability_async(net.n, arcs, p_dev.data_ptr(), net.s, net.t, R_dev.data_ptr(),
+                                c_dev.data_ptr(), st_dev.data_ptr(), stream)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    kern_ms = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+        kern_ms.append(B.bat_last_launch().kernel_ms)   # HIP events on the launch stream
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    R = float(R_dev.item())
+    count = int(c_dev.item())
+    assert int(st_dev.item()) == 0
+    assert count == cnt_cold and R == R_cold, "bench runs disagree"
+
+    # warm time-to-R through the synchronous host entry point
+    t0 = time.perf_counter()
+    R_w, _ = B.bat_reliability(net.n, arcs, net.p, net.s, net.t)
+    warm_s = time.perf_counter() - t0
+    li = B.bat_last_launch()
+
+    out = {
+        "metric": "arc-state vectors/s (G/s) + time-to-exact-R at m=40; fwd+grad vs fwd",
+        "value": nvec / (ms_per_step / 1e3) / 1e9,
+        "unit": "Gvec/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32 bit-sliced connectivity + f64 accumulation",
+        "data": "synthetic",
+        "config": {"workload": "5x5 grid, m=40 undirected arcs, corner to corner, p~U[0.85,0.99] "
+                               "(seed 220909711/2), 2^40 state vectors, plain forward",
+                   "vectors_per_step": nvec},
+        "R": R,
+        "R_hex": R.hex(),
+        "feasible_count": count,
+        "time_to_exact_R_s": {"cold_incl_jit": cold_s, "warm": warm_s, "jit_compile_ms": jit_ms},
+        "kernel_ms_mean": float(np.mean(kern_ms)),
+        "specialised_kernel": bool(li.specialised),
+        "relaxations_per_sweep": li.relaxations,
+    }
+
+    if not a.no_extras:
+        c4 = W.config4()
+        B.bat_reliability(c4.n, c4.arcs, c4.p, c4.s, c4.t)          # warm both kernels
+        B.bat_reliability_grad(c4.n, c4.arcs, c4.p, c4.s, c4.t)
+        fw, gr = [], []
+        for _ in range(3):
+            B.bat_reliability(c4.n, c4.arcs, c4.p, c4.s, c4.t)
+            fw.append(B.bat_last_launch().kernel_ms)
+            B.bat_reliability_grad(c4.n, c4.arcs, c4.p, c4.s, c4.t)
+            gr.append(B.bat_last_launch().kernel_ms)
+        out["fwd_grad_vs_fwd"] = {"workload": "random n=18 m=36 (seed 220909711/4), R + 36 gradients",
+                                  "fwd_kernel_ms": min(fw), "fwd_grad_kernel_ms": min(gr),
+                                  "ratio": min(gr) / min(fw)}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(net, a.cpu_sample_log2)
+        out["cpu_baseline"] = {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["projected_time_to_R_s"] = cpu["projected_time_to_R_s"]
+
+    # roofline of the enumeration kernel: integer ALU bound (no HBM traffic
+    # per vector, no contraction).  Algorithmic work per state vector = the
+    # layered search's arc inspections (oracle-measured mean on the sample),
+    # one bit-operation each.
+    kern_s = float(np.mean(kern_ms)) / 1e3
+    insp = cpu["inspections_per_vector"] if cpu else None
+    if insp is not None:
+        achieved = nvec * insp / kern_s
+        out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_BIT_OPS / 1e12,
+                           "unit": "Tbitop/s", "frac": achieved / PEAK_BIT_OPS, "traffic": None,
+                           "work_per_vector": insp, "work_unit": "PLSA arc inspections (1 bit-op each)"}
+    line = json.dumps(out)
+    print(line, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * bat.h -- C ABI of the MI355X (gfx950) library for exact two-terminal
+ * reliability of binary-state networks by exhaustive binary-addition-tree
+ * enumeration (BAT, Yeh, arXiv 2209.09711).
+ *
+ * What every entry point computes (Section 3, Eq. 1):
+ *
+ *   R = sum over all X in {0,1}^m with s ~ t in G(X) of  prod_i q_i(x_i),
+ *   q_i(1) = p_i,  q_i(0) = 1 - p_i,
+ *
+ * where G(X) keeps the arcs a_i with x_i = 1 (Section 2.2) and "s ~ t" is
+ * the PLSA connectivity test of Section 3.2 (arcs are undirected).  The
+ * feasible-vector count is the number of such X.  The enumeration order is
+ * the paper's backward BAT (Section 3.1, Table 2): arc i (0-based) is the
+ * coordinate x_{i+1}, the vector with 0-based index c has x_{i+1} = bit
+ * (m-1-i) of c (Eq. 2-3), so arc 0 is the most significant coordinate.
+ *
+ * The gradient entry points add dR/dp_i = T1_i - T0_i, where T1_i (T0_i) is
+ * R with p_i replaced by 1 (by 0): Eq. 1 is multilinear in p, so these are
+ * the Birnbaum importances.  They come from the same sweep as R (each
+ * connectivity verdict is reused), not from extra runs.
+ *
+ * Conventions for every function:
+ *  - Nodes are 0-based ids in [0, n_nodes).  The paper's source 1 and sink n
+ *    are passed explicitly as s and t (s != t).
+ *  - arcs points to n_arcs pairs (u, v) (bat_arc), undirected.  Self-loops
+ *    and parallel arcs are accepted (Eq. 1 is well defined for them; the
+ *    paper's assumption of none restricts its benchmarks only).
+ *  - p[i] is the working probability of arcs[i]; it must be finite and in
+ *    [0, 1].
+ *  - Limits: 2 <= n_nodes <= BAT_MAX_NODES, 0 <= n_arcs <= BAT_MAX_ARCS.
+ *    m = 0 is one empty, disconnected vector: R = 0, count = 0.
+ *  - Return value: BAT_OK (0) or a negative BAT_E* code.  On error the
+ *    outputs are left untouched and bat_last_error() describes the failure.
+ *  - Ownership: the caller owns every buffer.  The library copies what it
+ *    needs during the call and keeps no pointer after it returns (for the
+ *    _async functions: after the work queued on the stream has run).
+ *  - Threads: calls are re-entrant; synchronous calls run on a per-thread
+ *    stream of the current HIP device, _async calls on the stream given.
+ *  - Results are deterministic: the same inputs give bitwise the same R,
+ *    count and gradient on every run (fixed-order reductions, no
+ *    floating-point atomics).
+ */
+#ifndef BAT_H
+#define BAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BAT_OK 0
+#define BAT_EINVAL (-1)  /* bad argument: sizes, node ids, s == t, p outside [0,1] or NaN, NULL */
+#define BAT_ETOOBIG (-2) /* n_nodes > BAT_MAX_NODES or n_arcs > BAT_MAX_ARCS */
+#define BAT_EDEVICE (-3) /* HIP runtime or JIT compiler error; text in bat_last_error() */
+#define BAT_ENOMEM (-4)  /* host or device allocation failed */
+
+#define BAT_MAX_NODES 64
+#define BAT_MAX_ARCS 62
+
+typedef struct {
+    int32_t u, v;
+} bat_arc;
+
+/* Library version string, e.g. "bat-mi355x 0.1.0". */
+const char *bat_version(void);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *bat_last_error(void);
+
+/*
+ * Exact reliability R and feasible-vector count of G(V, E, D_b) between s
+ * and t (Eq. 1 over all 2^m vectors).  Host pointers; blocks until done.
+ */
+int bat_reliability(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const double *p,
+                    int32_t s, int32_t t, double *R_out, uint64_t *count_out);
+
+/*
+ * As bat_reliability, plus dR/dp (n_arcs doubles) from the same sweep.
+ * T1_out and T0_out (n_arcs doubles each, may be NULL) receive T1_i =
+ * R|p_i<-1 and T0_i = R|p_i<-0; dRdp_out[i] = T1_i - T0_i.
+ */
+int bat_reliability_grad(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const double *p,
+                         int32_t s, int32_t t, double *R_out, uint64_t *count_out,
+                         double *dRdp_out, double *T1_out, double *T0_out);
+
+/*
+ * Partial sums over the 0-based backward-order indices [c_lo, c_hi) of the
+ * 2^m vectors (c_lo <= c_hi <= 2^m).  The equal divisions of Section 4 (Eq.
+ * 6: division i of chi holds indices [(i-1) mu, i mu), mu = 2^m / chi) are
+ * such ranges, so a long sweep can be split into checkpointed chunks or
+ * shards and the parts added afterwards.  The sum is returned unevaluated
+ * as a double-double (*R_hi + *R_lo).  T1_out / T0_out (n_arcs doubles each)
+ * may both be NULL (no gradient) or both non-NULL (gradient partials,
+ * collapsed to doubles).
+ */
+int bat_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const double *p,
+                          int32_t s, int32_t t, uint64_t c_lo, uint64_t c_hi,
+                          double *R_hi, double *R_lo, uint64_t *count_out,
+                          double *T1_out, double *T0_out);
+
+/*
+ * Many networks, many probability vectors, one persistent launch.
+ * Graph g has n_nodes[g] nodes and the arcs arcs[arc_offsets[g] ..
+ * arc_offsets[g+1]) (arc_offsets has n_graphs + 1 entries, arc_offsets[0]
+ * = 0), source s[g], sink t[g].  Each graph has n_pvec probability vectors:
+ * p holds, graph after graph, an n_pvec x m_g row-major block (arc fastest),
+ * i.e. graph g's block starts at n_pvec * arc_offsets[g].  One connectivity
+ * verdict per state vector serves all n_pvec probability vectors of its
+ * graph.  Outputs: R_out[g * n_pvec + j] and counts_out[g].  Limits per
+ * graph as above; 1 <= n_pvec <= BAT_MAX_PVEC.
+ */
+#define BAT_MAX_PVEC 64
+int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_offsets,
+                            const bat_arc *arcs, const int32_t *s, const int32_t *t,
+                            int32_t n_pvec, const double *p, double *R_out, uint64_t *counts_out);
+
+/*
+ * Stream-ordered forms for callers that keep p and the results in device
+ * memory (e.g. PyTorch tensors).  arcs, n_nodes, s, t are host values; p_dev
+ * (n_arcs doubles), R_dev (1 double), count_dev (1 uint64) and, for the
+ * gradient form, dRdp_dev / T1_dev / T0_dev (n_arcs doubles each; T1_dev and
+ * T0_dev may be NULL) are device pointers on the current device.  stream is
+ * a hipStream_t (NULL = the default stream).  The call returns once the
+ * work is queued; argument errors that need no device data are returned at
+ * once.  p_dev is checked on the device: if any p is outside [0, 1] or NaN,
+ * *R_dev is set to NaN and, when status_dev is non-NULL, *status_dev to
+ * BAT_EINVAL (else BAT_OK).  Temporary device memory is taken from the
+ * stream-ordered allocator and released on the stream.
+ */
+int bat_reliability_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs,
+                          const double *p_dev, int32_t s, int32_t t, double *R_dev,
+                          uint64_t *count_dev, int32_t *status_dev, void *stream);
+
+int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs,
+                               const double *p_dev, int32_t s, int32_t t, double *R_dev,
+                               uint64_t *count_dev, double *dRdp_dev, double *T1_dev,
+                               double *T0_dev, int32_t *status_dev, void *stream);
+
+/*
+ * Tuning and diagnostics.
+ *
+ * bat_set_option / bat_get_option read and set process-wide knobs (also
+ * settable through the environment variable of the same name at load):
+ *   "BAT_JIT"          0 = never use graph-specialised kernels, 1 = always,
+ *                      2 = automatic (default: when the problem is large)
+ *   "BAT_CHUNK_LOG2"   log2 of the enumeration iterations per wavefront
+ *                      work item (0 = automatic)
+ *   "BAT_SEG_LOG2"     log2 of the iterations per probability segment
+ *   "BAT_CHECK_EVERY"  1 = convergence test after every sweep, 2 = after
+ *                      every forward+backward pair
+ *   "BAT_AUTOTUNE"     1 = let bat_autotune's cached choices apply
+ * Unknown keys return BAT_EINVAL.
+ */
+int bat_set_option(const char *key, int64_t value);
+int bat_get_option(const char *key, int64_t *value);
+
+/*
+ * Autotuner: times the kernel variants (work-item size, convergence-test
+ * cadence, specialised vs generic kernel) on an evenly spread sample of the
+ * counter range of this graph and caches the fastest choice under the
+ * graph's structure.  Later calls on a graph of the same structure use it
+ * while "BAT_AUTOTUNE" is 1.  *best_ns_per_vector (may be NULL) receives the
+ * best measured time per state vector.  Results never depend on the choice
+ * beyond floating-point rounding; counts never change.
+ */
+int bat_autotune(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const double *p,
+                 int32_t s, int32_t t, double *best_ns_per_vector);
+
+/*
+ * Description of the last launch on the calling thread, for benchmarks:
+ * kernel time in milliseconds (HIP events around the enumeration kernel on
+ * its own stream), the number of state vectors it covered and whether the
+ * graph-specialised kernel ran.  Returns BAT_EINVAL if nothing ran yet.
+ */
+typedef struct {
+    double kernel_ms;      /* enumeration kernel only */
+    double total_ms;       /* tables + enumeration + reduction, device side */
+    double jit_ms;         /* graph-specialised kernel compile time (0 if cached / unused) */
+    uint64_t vectors;      /* state vectors covered */
+    int32_t specialised;   /* 1 if the graph-specialised kernel ran */
+    int32_t chunk_log2;    /* work-item size used */
+    int32_t n_chunks;      /* wavefront work items */
+    int32_t relaxations;   /* arc relaxations per sweep after pruning */
+} bat_launch_info;
+
+int bat_last_launch(bat_launch_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BAT_H */

@@ -1,0 +1,252 @@
+"""MI355X-native exact two-terminal reliability by binary-addition-tree
+enumeration (BAT, arXiv 2209.09711): Python binding of ``libbat_hip.so``.
+
+Every function here only marshals arguments for the C ABI declared in
+``include/bat.h`` (same names); all enumeration, connectivity and
+probability arithmetic runs in the HIP kernels.  There is no CPU fallback:
+if the library is missing, importing this package raises ``ImportError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbat_hip.so")
+
+BAT_OK = 0
+BAT_EINVAL = -1
+BAT_ETOOBIG = -2
+BAT_EDEVICE = -3
+BAT_ENOMEM = -4
+BAT_MAX_NODES = 64
+BAT_MAX_ARCS = 62
+BAT_MAX_PVEC = 64
+
+# Every entry point of include/bat.h.
+EXPORTED = ("bat_version", "bat_last_error", "bat_reliability", "bat_reliability_grad",
+            "bat_reliability_range", "bat_reliability_batched", "bat_reliability_async",
+            "bat_reliability_grad_async", "bat_set_option", "bat_get_option", "bat_autotune",
+            "bat_last_launch")
+
+
+class bat_arc(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_int32), ("v", ctypes.c_int32)]
+
+
+class bat_launch_info(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("jit_ms", ctypes.c_double), ("vectors", ctypes.c_uint64),
+                ("specialised", ctypes.c_int32), ("chunk_log2", ctypes.c_int32),
+                ("n_chunks", ctypes.c_int32), ("relaxations", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                          f"g.build()'` (the HIP library is required; there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, u64, i64, dbl = ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_double
+    P = ctypes.c_void_p
+    sig = {
+        "bat_version": ([], ctypes.c_char_p),
+        "bat_last_error": ([], ctypes.c_char_p),
+        "bat_reliability": ([i32, i32, P, P, i32, i32, P, P], ctypes.c_int),
+        "bat_reliability_grad": ([i32, i32, P, P, i32, i32, P, P, P, P, P], ctypes.c_int),
+        "bat_reliability_range": ([i32, i32, P, P, i32, i32, u64, u64, P, P, P, P, P], ctypes.c_int),
+        "bat_reliability_batched": ([i32, P, P, P, P, P, i32, P, P, P], ctypes.c_int),
+        "bat_reliability_async": ([i32, i32, P, P, i32, i32, P, P, P, P], ctypes.c_int),
+        "bat_reliability_grad_async": ([i32, i32, P, P, i32, i32, P, P, P, P, P, P, P], ctypes.c_int),
+        "bat_set_option": ([ctypes.c_char_p, i64], ctypes.c_int),
+        "bat_get_option": ([ctypes.c_char_p, P], ctypes.c_int),
+        "bat_autotune": ([i32, i32, P, P, i32, i32, P], ctypes.c_int),
+        "bat_last_launch": ([P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+class BatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"BAT error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != BAT_OK:
+        raise BatError(rc, _lib.bat_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _arcs(arcs) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(arcs, dtype=np.int32).reshape(-1, 2))
+    return a
+
+
+def _p(p, m) -> np.ndarray:
+    pv = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(-1))
+    if pv.shape[0] != m:
+        raise ValueError(f"p has {pv.shape[0]} entries for {m} arcs")
+    return pv
+
+
+# ------------------------------------------------------------ thin C names
+
+def bat_version() -> str:
+    return _lib.bat_version().decode()
+
+
+def bat_last_error() -> str:
+    return _lib.bat_last_error().decode()
+
+
+def bat_reliability(n_nodes: int, arcs, p, s: int, t: int) -> Tuple[float, int]:
+    """(R, feasible-vector count) of Eq. 1; arcs as (m, 2) node pairs."""
+    a = _arcs(arcs)
+    pv = _p(p, a.shape[0])
+    R = ctypes.c_double(0.0)
+    cnt = ctypes.c_uint64(0)
+    _check(_lib.bat_reliability(n_nodes, a.shape[0], _ptr(a), _ptr(pv), s, t, ctypes.byref(R), ctypes.byref(cnt)))
+    return R.value, cnt.value
+
+
+@dataclass
+class GradResult:
+    R: float
+    count: int
+    dRdp: np.ndarray
+    T1: np.ndarray
+    T0: np.ndarray
+
+
+def bat_reliability_grad(n_nodes: int, arcs, p, s: int, t: int) -> GradResult:
+    a = _arcs(arcs)
+    m = a.shape[0]
+    pv = _p(p, m)
+    R = ctypes.c_double(0.0)
+    cnt = ctypes.c_uint64(0)
+    g = np.zeros(max(m, 1))
+    T1 = np.zeros(max(m, 1))
+    T0 = np.zeros(max(m, 1))
+    _check(_lib.bat_reliability_grad(n_nodes, m, _ptr(a), _ptr(pv), s, t, ctypes.byref(R), ctypes.byref(cnt),
+                                     _ptr(g), _ptr(T1), _ptr(T0)))
+    return GradResult(R.value, cnt.value, g[:m], T1[:m], T0[:m])
+
+
+@dataclass
+class RangeResult:
+    R_hi: float
+    R_lo: float
+    count: int
+    T1: Optional[np.ndarray]
+    T0: Optional[np.ndarray]
+
+    @property
+    def R(self) -> float:
+        return self.R_hi + self.R_lo
+
+
+def bat_reliability_range(n_nodes: int, arcs, p, s: int, t: int, c_lo: int, c_hi: int,
+                          grad: bool = False) -> RangeResult:
+    a = _arcs(arcs)
+    m = a.shape[0]
+    pv = _p(p, m)
+    hi = ctypes.c_double(0.0)
+    lo = ctypes.c_double(0.0)
+    cnt = ctypes.c_uint64(0)
+    T1 = np.zeros(max(m, 1)) if grad else None
+    T0 = np.zeros(max(m, 1)) if grad else None
+    _check(_lib.bat_reliability_range(n_nodes, m, _ptr(a), _ptr(pv), s, t, int(c_lo), int(c_hi),
+                                      ctypes.byref(hi), ctypes.byref(lo), ctypes.byref(cnt), _ptr(T1), _ptr(T0)))
+    return RangeResult(hi.value, lo.value, cnt.value, None if T1 is None else T1[:m], None if T0 is None else T0[:m])
+
+
+def bat_reliability_batched(graphs: Sequence[Tuple[int, object, int, int]], p_blocks: Sequence[np.ndarray]):
+    """graphs: [(n_nodes, arcs, s, t)], p_blocks[g]: (n_pvec, m_g) array.
+    Returns (R[n_graphs, n_pvec], counts[n_graphs])."""
+    G = len(graphs)
+    if G == 0:
+        raise ValueError("no graphs")
+    n_pvec = int(np.asarray(p_blocks[0]).shape[0])
+    nn = np.asarray([g[0] for g in graphs], dtype=np.int32)
+    arcs_l = [_arcs(g[1]) for g in graphs]
+    off = np.zeros(G + 1, dtype=np.int32)
+    off[1:] = np.cumsum([a.shape[0] for a in arcs_l])
+    arcs = np.ascontiguousarray(np.concatenate(arcs_l, axis=0) if off[-1] else np.zeros((1, 2), np.int32))
+    ss = np.asarray([g[2] for g in graphs], dtype=np.int32)
+    tt = np.asarray([g[3] for g in graphs], dtype=np.int32)
+    blocks = []
+    for g, pb in enumerate(p_blocks):
+        pb = np.asarray(pb, dtype=np.float64)
+        if pb.shape != (n_pvec, arcs_l[g].shape[0]):
+            raise ValueError(f"p block {g} has shape {pb.shape}, want {(n_pvec, arcs_l[g].shape[0])}")
+        blocks.append(pb.reshape(-1))
+    p = np.ascontiguousarray(np.concatenate(blocks) if blocks else np.zeros(1))
+    R = np.zeros(G * n_pvec)
+    cnt = np.zeros(G, dtype=np.uint64)
+    _check(_lib.bat_reliability_batched(G, _ptr(nn), _ptr(off), _ptr(arcs), _ptr(ss), _ptr(tt), n_pvec, _ptr(p),
+                                        _ptr(R), _ptr(cnt)))
+    return R.reshape(G, n_pvec), cnt
+
+
+def bat_set_option(key: str, value: int):
+    _check(_lib.bat_set_option(key.encode(), int(value)))
+
+
+def bat_get_option(key: str) -> int:
+    v = ctypes.c_int64(0)
+    _check(_lib.bat_get_option(key.encode(), ctypes.byref(v)))
+    return v.value
+
+
+def bat_autotune(n_nodes: int, arcs, p, s: int, t: int) -> float:
+    """Tune the launch for this graph structure; returns ns per state vector."""
+    a = _arcs(arcs)
+    pv = _p(p, a.shape[0])
+    ns = ctypes.c_double(0.0)
+    _check(_lib.bat_autotune(n_nodes, a.shape[0], _ptr(a), _ptr(pv), s, t, ctypes.byref(ns)))
+    return ns.value
+
+
+def bat_last_launch() -> bat_launch_info:
+    info = bat_launch_info()
+    _check(_lib.bat_last_launch(ctypes.byref(info)))
+    return info
+
+
+def bat_reliability_async(n_nodes: int, arcs, p_dev_ptr: int, s: int, t: int, R_dev_ptr: int,
+                          count_dev_ptr: int, status_dev_ptr: Optional[int], stream: int):
+    a = _arcs(arcs)
+    _check(_lib.bat_reliability_async(n_nodes, a.shape[0], _ptr(a), p_dev_ptr, s, t, R_dev_ptr, count_dev_ptr,
+                                      status_dev_ptr, stream))
+
+
+def bat_reliability_grad_async(n_nodes: int, arcs, p_dev_ptr: int, s: int, t: int, R_dev_ptr: int,
+                               count_dev_ptr: int, dRdp_dev_ptr: int, T1_dev_ptr: Optional[int],
+                               T0_dev_ptr: Optional[int], status_dev_ptr: Optional[int], stream: int):
+    a = _arcs(arcs)
+    _check(_lib.bat_reliability_grad_async(n_nodes, a.shape[0], _ptr(a), p_dev_ptr, s, t, R_dev_ptr,
+                                           count_dev_ptr, dRdp_dev_ptr, T1_dev_ptr, T0_dev_ptr, status_dev_ptr,
+                                           stream))
+
+
+# ------------------------------------------------------------ friendly names
+reliability = bat_reliability
+reliability_grad = bat_reliability_grad
+reliability_range = bat_reliability_range
+reliability_batched = bat_reliability_batched
+autotune = bat_autotune
+version = bat_version

@@ -1,0 +1,806 @@
+// bat_host.cpp -- the C ABI declared in include/bat.h.
+//
+// Per call: validate -> plan (which arcs can matter, sweep order, launch
+// shape) -> queue on one stream: probability tables from p (on the device),
+// the enumeration kernel over the counter range, a fixed-order reduction of
+// the per-work-item partials, and either a copy back (synchronous entry
+// points) or a finalize kernel into the caller's device buffers (_async).
+//
+// The enumeration kernel is the template in bat_device.hpp, instantiated
+// either ahead of time with the graph read at run time (k_fwd_dyn /
+// k_grad_dyn) or at run time through hiprtc with the graph's arcs as
+// compile-time constants, so that every node's reach word lives in a fixed
+// register (bat_fwd_jit / bat_grad_jit).  Compiled modules are cached per
+// (device, graph structure, kernel kind).
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bat.h"
+#include "bat_launch.hpp"
+
+using bat::u32;
+using bat::u64;
+
+
+namespace {
+
+const char *kVersion = "bat-mi355x 0.1.0";
+
+#include "bat_device_embed.inc"  // kDeviceSource: bat_device.hpp as text
+
+// ------------------------------------------------------------ errors
+thread_local std::string t_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? BAT_ENOMEM : BAT_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                   \
+    } while (0)
+
+// ------------------------------------------------------------ options
+struct Options {
+    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1};
+    Options()
+    {
+        auto rd = [](const char *k, std::atomic<int64_t> &v) {
+            const char *e = getenv(k);
+            if (e && *e) v = strtoll(e, nullptr, 10);
+        };
+        rd("BAT_JIT", jit);
+        rd("BAT_CHUNK_LOG2", chunk_log2);
+        rd("BAT_SEG_LOG2", seg_log2);
+        rd("BAT_CHECK_EVERY", check_every);
+        rd("BAT_AUTOTUNE", autotune);
+    }
+    std::atomic<int64_t> *find(const char *k)
+    {
+        if (!k) return nullptr;
+        if (!strcmp(k, "BAT_JIT")) return &jit;
+        if (!strcmp(k, "BAT_CHUNK_LOG2")) return &chunk_log2;
+        if (!strcmp(k, "BAT_SEG_LOG2")) return &seg_log2;
+        if (!strcmp(k, "BAT_CHECK_EVERY")) return &check_every;
+        if (!strcmp(k, "BAT_AUTOTUNE")) return &autotune;
+        return nullptr;
+    }
+};
+Options &opts()
+{
+    static Options o;
+    return o;
+}
+
+// ------------------------------------------------------------ validation
+int validate(int32_t n, int32_t m, const bat_arc *arcs, const double *p_host, int32_t s, int32_t t)
+{
+    if (n < 2) return fail(BAT_EINVAL, "n_nodes must be >= 2 (got %d)", n);
+    if (m < 0) return fail(BAT_EINVAL, "n_arcs must be >= 0 (got %d)", m);
+    if (n > BAT_MAX_NODES) return fail(BAT_ETOOBIG, "n_nodes %d exceeds %d", n, BAT_MAX_NODES);
+    if (m > BAT_MAX_ARCS) return fail(BAT_ETOOBIG, "n_arcs %d exceeds %d", m, BAT_MAX_ARCS);
+    if (s < 0 || s >= n || t < 0 || t >= n) return fail(BAT_EINVAL, "s=%d or t=%d outside [0,%d)", s, t, n);
+    if (s == t) return fail(BAT_EINVAL, "s and t must differ (both %d)", s);
+    if (m > 0 && !arcs) return fail(BAT_EINVAL, "arcs is NULL");
+    for (int32_t i = 0; i < m; ++i)
+        if (arcs[i].u < 0 || arcs[i].u >= n || arcs[i].v < 0 || arcs[i].v >= n)
+            return fail(BAT_EINVAL, "arc %d = (%d,%d) has a node outside [0,%d)", i, arcs[i].u, arcs[i].v, n);
+    if (p_host)
+        for (int32_t i = 0; i < m; ++i)
+            if (!(p_host[i] >= 0.0 && p_host[i] <= 1.0))
+                return fail(BAT_EINVAL, "p[%d] = %g is not a probability", i, p_host[i]);
+    return BAT_OK;
+}
+
+// ------------------------------------------------------------ planning
+// Arcs that lie on some simple s-t path: exactly those in the biconnected
+// component of the graph plus a virtual arc (s, t) that contains the
+// virtual arc (two edges share a biconnected component iff a simple cycle
+// passes through both).  Every other arc never changes whether s reaches t,
+// so the sweeps skip it; its state is still enumerated and weighted.
+struct Bcc {
+    int n, m;
+    std::vector<std::vector<std::pair<int, int>>> adj;
+    std::vector<int> disc, low, stk;
+    std::vector<char> rel;
+    int timer = 0;
+    void dfs(int u, int pe)
+    {
+        disc[u] = low[u] = ++timer;
+        for (auto [v, e] : adj[u]) {
+            if (e == pe) continue;
+            if (!disc[v]) {
+                stk.push_back(e);
+                dfs(v, e);
+                low[u] = std::min(low[u], low[v]);
+                if (low[v] >= disc[u]) {
+                    std::vector<int> comp;
+                    for (;;) {
+                        int x = stk.back();
+                        stk.pop_back();
+                        comp.push_back(x);
+                        if (x == e) break;
+                    }
+                    bool has_virtual = false;
+                    for (int x : comp) has_virtual |= (x == m);
+                    if (has_virtual)
+                        for (int x : comp)
+                            if (x < m) rel[x] = 1;
+                }
+            } else if (disc[v] < disc[u]) {
+                stk.push_back(e);
+                low[u] = std::min(low[u], disc[v]);
+            }
+        }
+    }
+};
+
+struct Plan {
+    int n = 0, m = 0, s = 0, t = 0;
+    int N = 0, S = 0, T = 0;              // relevant nodes, renumbered
+    std::vector<int> ru, rv, rb;          // relaxations (forward order): nodes and counter bit
+    std::vector<u32> code, wconst;        // the same for the generic kernel
+    std::string structure;                // JIT key (graph structure only)
+};
+
+void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, Plan &P)
+{
+    P.n = n;
+    P.m = m;
+    P.s = s;
+    P.t = t;
+    Bcc B;
+    B.n = n;
+    B.m = m;
+    B.adj.assign(n, {});
+    for (int i = 0; i < m; ++i) {
+        int u = arcs[i].u, v = arcs[i].v;
+        if (u == v) continue;  // a self-loop never joins two nodes
+        B.adj[u].push_back({v, i});
+        B.adj[v].push_back({u, i});
+    }
+    B.adj[s].push_back({t, m});
+    B.adj[t].push_back({s, m});
+    B.disc.assign(n, 0);
+    B.low.assign(n, 0);
+    B.rel.assign(m + 1, 0);
+    B.dfs(s, -1);
+
+    // BFS from s over relevant arcs: node numbering and sweep order
+    std::vector<int> id(n, -1), order;
+    std::vector<char> listed(m, 0);
+    id[s] = 0;
+    order.push_back(s);
+    P.ru.clear(); P.rv.clear(); P.rb.clear();
+    for (size_t h = 0; h < order.size(); ++h) {
+        int u = order[h];
+        for (int i = 0; i < m; ++i) {
+            if (!B.rel[i] || listed[i]) continue;
+            int a = arcs[i].u, b = arcs[i].v;
+            if (a != u && b != u) continue;
+            int w = (a == u) ? b : a;
+            if (id[w] < 0) {
+                id[w] = (int)order.size();
+                order.push_back(w);
+            }
+            listed[i] = 1;
+            P.ru.push_back(id[u]);
+            P.rv.push_back(id[w]);
+            P.rb.push_back(m - 1 - i);
+        }
+    }
+    if (id[t] < 0) {  // s and t never connected: keep both as nodes, no arcs
+        id[t] = (int)order.size();
+        order.push_back(t);
+    }
+    P.N = (int)order.size();
+    P.S = 0;
+    P.T = id[t];
+    P.code.resize(P.ru.size());
+    P.wconst.resize(P.ru.size());
+    for (size_t k = 0; k < P.ru.size(); ++k) {
+        P.code[k] = (u32)P.ru[k] | ((u32)P.rv[k] << 6) | ((u32)P.rb[k] << 12);
+        P.wconst[k] = P.rb[k] < bat::kSliceBits ? bat::slice_pattern(P.rb[k]) : 0u;
+    }
+    std::string sdesc = "N" + std::to_string(P.N) + " S" + std::to_string(P.S) + " T" + std::to_string(P.T) +
+                        " m" + std::to_string(m) + " :";
+    for (size_t k = 0; k < P.ru.size(); ++k)
+        sdesc += " " + std::to_string(P.ru[k]) + "," + std::to_string(P.rv[k]) + "," + std::to_string(P.rb[k]);
+    P.structure = sdesc;
+}
+
+// ------------------------------------------------------------ device state
+struct DeviceInfo {
+    int id = -1;
+    int cus = 0;
+    std::string arch;
+};
+
+int current_device(DeviceInfo &D)
+{
+    static std::mutex mu;
+    static std::map<int, DeviceInfo> cache;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it == cache.end()) {
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, dev));
+        DeviceInfo d;
+        d.id = dev;
+        d.cus = prop.multiProcessorCount;
+        d.arch = prop.gcnArchName;
+        it = cache.emplace(dev, d).first;
+    }
+    D = it->second;
+    return BAT_OK;
+}
+
+struct ThreadState {
+    std::map<int, hipStream_t> streams;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool have_launch = false;
+    bat_launch_info info{};
+    ~ThreadState()
+    {
+        // streams and events belong to the process's HIP runtime, which may
+        // already be torn down at thread exit; they are released with it.
+    }
+};
+thread_local ThreadState t_state;
+
+int thread_stream(int dev, hipStream_t &s)
+{
+    auto it = t_state.streams.find(dev);
+    if (it == t_state.streams.end()) {
+        hipStream_t st;
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        it = t_state.streams.emplace(dev, st).first;
+    }
+    s = it->second;
+    return BAT_OK;
+}
+
+int events_ready()
+{
+    if (!t_state.ev[0])
+        for (auto &e : t_state.ev) HIPCHK(hipEventCreate(&e));
+    return BAT_OK;
+}
+
+// ------------------------------------------------------------ JIT cache
+struct JitEntry {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+};
+std::mutex g_jit_mu;
+std::map<std::string, JitEntry> g_jit;
+
+std::string jit_source(const Plan &P, bool grad)
+{
+    std::string s;
+    s.reserve(strlen(kDeviceSource) + 4096);
+    s += kDeviceSource;
+    s += "\nstruct JitGraph {\n";
+    s += "  static constexpr int N = " + std::to_string(P.N) + ";\n";
+    s += "  static constexpr int S = " + std::to_string(P.S) + ";\n";
+    s += "  static constexpr int T = " + std::to_string(P.T) + ";\n";
+    size_t nr = P.ru.size();
+    s += "  static constexpr int NR = " + std::to_string(nr) + ";\n";
+    auto arr = [&](const char *name, const std::vector<int> &v) {
+        s += std::string("  static constexpr unsigned char ") + name + "[" + std::to_string(nr ? nr : 1) + "] = {";
+        if (nr == 0) s += "0";
+        for (size_t k = 0; k < nr; ++k) s += (k ? "," : "") + std::to_string(v[k]);
+        s += "};\n";
+    };
+    arr("RU", P.ru);
+    arr("RV", P.rv);
+    arr("RB", P.rb);
+    s += "};\n";
+    if (grad)
+        s += "extern \"C\" __global__ void __launch_bounds__(256) bat_grad_jit(bat::KParams P) {\n"
+             "  __shared__ bat::LdsTables L; __shared__ bat::LdsGrad LG;\n"
+             "  bat::sweep_kernel<bat::StaticClosure<JitGraph>, true>(P, L, &LG);\n}\n";
+    else
+        s += "extern \"C\" __global__ void __launch_bounds__(256) bat_fwd_jit(bat::KParams P) {\n"
+             "  __shared__ bat::LdsTables L;\n"
+             "  bat::sweep_kernel<bat::StaticClosure<JitGraph>, false>(P, L, nullptr);\n}\n";
+    return s;
+}
+
+int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, double &compile_ms)
+{
+    compile_ms = 0.0;
+    std::string key = std::to_string(D.id) + (grad ? " grad " : " fwd ") + P.structure;
+    std::lock_guard<std::mutex> lk(g_jit_mu);
+    auto it = g_jit.find(key);
+    if (it != g_jit.end()) {
+        fn = it->second.fn;
+        return BAT_OK;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    std::string src = jit_source(P, grad);
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "bat_jit.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+        return fail(BAT_EDEVICE, "hiprtcCreateProgram failed");
+    std::string arch = "--offload-arch=" + D.arch;
+    const char *o[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    hiprtcResult rc = hiprtcCompileProgram(prog, 7, o);
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls + 1, '\0');
+        hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return fail(BAT_EDEVICE, "hiprtc compile failed (%s): %.800s", hiprtcGetErrorString(rc), log.c_str());
+    }
+    size_t sz = 0;
+    hiprtcGetCodeSize(prog, &sz);
+    std::vector<char> code(sz);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    JitEntry e;
+    HIPCHK(hipModuleLoadData(&e.mod, code.data()));
+    HIPCHK(hipModuleGetFunction(&e.fn, e.mod, grad ? "bat_grad_jit" : "bat_fwd_jit"));
+    g_jit.emplace(key, e);
+    fn = e.fn;
+    compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return BAT_OK;
+}
+
+// ------------------------------------------------------------ autotune cache
+struct TuneChoice {
+    int chunk_log2, check_every, jit;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune;
+
+// ------------------------------------------------------------ the sweep
+struct Request {
+    int32_t n, m, s, t;
+    const bat_arc *arcs;
+    const double *p_dev;    // device probabilities
+    u64 c_lo, c_hi;
+    bool grad;
+    // forced knobs (autotuner); -1 = from options
+    int force_chunk_log2 = -1, force_check = -1, force_jit = -1;
+};
+
+struct Launch {
+    void *ws = nullptr;     // workspace (stream-ordered)
+    double *res = nullptr;  // [ncol][2]
+    u64 *count = nullptr;
+    int *status = nullptr;
+    u32 ncol = 1;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Queue tables + sweep + reduce on `stream`.  Allocates the workspace with
+// hipMallocAsync; the caller frees it on the same stream.
+int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream_t stream, Launch &L)
+{
+    const u32 m = (u32)rq.m;
+    const u32 ubits = m > (u32)bat::kWordBits ? m - bat::kWordBits : 0u;
+    const u64 g_first = rq.c_lo >> bat::kWordBits;
+    const u64 g_last = (rq.c_hi - 1) >> bat::kWordBits;
+    const u64 iters = g_last - g_first + 1;
+
+    Options &O = opts();
+    TuneChoice tc{(int)O.chunk_log2.load(), (int)O.check_every.load(), (int)O.jit.load()};
+    if (O.autotune.load()) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(std::to_string(D.id) + (rq.grad ? " grad " : " fwd ") + P.structure);
+        if (it != g_tune.end()) tc = it->second;
+    }
+    if (rq.force_chunk_log2 >= 0) tc.chunk_log2 = rq.force_chunk_log2;
+    if (rq.force_check >= 0) tc.check_every = rq.force_check;
+    if (rq.force_jit >= 0) tc.jit = rq.force_jit;
+
+    int clog = tc.chunk_log2;
+    if (clog <= 0) {  // aim at ~64 work items per CU, at most 4096 iterations each
+        u64 target = iters / ((u64)std::max(D.cus, 1) * 64ull);
+        clog = 0;
+        while (clog < 12 && (2ull << clog) <= target) ++clog;
+    }
+    clog = std::min(clog, 20);
+    u32 f = (u32)std::max<int64_t>(0, std::min<int64_t>(O.seg_log2.load(), bat::kMaxSegLog));
+    if (f > ubits) f = ubits;
+
+    bat::KParams K;
+    memset(&K, 0, sizeof K);
+    K.c_lo = rq.c_lo;
+    K.c_hi = rq.c_hi;
+    K.g_first = g_first;
+    K.g_last = g_last;
+    K.chunk_iters = 1ull << clog;
+    K.n_chunks = (iters + K.chunk_iters - 1) >> clog;
+    K.m = m;
+    K.ubits = ubits;
+    K.seg_log = f;
+    K.check_every = tc.check_every >= 2 ? 2u : 1u;
+    K.ncol = rq.grad ? 1u + 2u * m : 1u;
+    K.n_nodes = (u32)P.N;
+    K.s = (u32)P.S;
+    K.t = (u32)P.T;
+    K.n_relax = (u32)P.code.size();
+    L.ncol = K.ncol;
+
+    // workspace: tables | status | relax | rw | partials | counts | res | count
+    size_t off = 0;
+    const size_t o_tab = off;
+    off = align_up(off + sizeof(double) * bat::kTables, 256);
+    const size_t o_st = off;
+    off = align_up(off + 64, 256);
+    const size_t o_rl = off;
+    off = align_up(off + sizeof(u32) * (P.code.size() + 1), 256);
+    const size_t o_rw = off;
+    off = align_up(off + sizeof(u32) * (P.code.size() + 1), 256);
+    const size_t o_part = off;
+    off = align_up(off + sizeof(double) * 2 * K.ncol * K.n_chunks, 256);
+    const size_t o_pc = off;
+    off = align_up(off + sizeof(u64) * K.n_chunks, 256);
+    const size_t o_res = off;
+    off = align_up(off + sizeof(double) * 2 * K.ncol, 256);
+    const size_t o_cnt = off;
+    off = align_up(off + sizeof(u64), 256);
+    char *ws = nullptr;
+    HIPCHK(hipMallocAsync((void **)&ws, off, stream));
+    L.ws = ws;
+    K.tables = (const double *)(ws + o_tab);
+    K.status = (const int *)(ws + o_st);
+    K.relax = (const u32 *)(ws + o_rl);
+    K.rw = (const u32 *)(ws + o_rw);
+    K.part = (double *)(ws + o_part);
+    K.pcount = (u64 *)(ws + o_pc);
+    L.res = (double *)(ws + o_res);
+    L.count = (u64 *)(ws + o_cnt);
+    L.status = (int *)(ws + o_st);
+    if (!P.code.empty()) {
+        HIPCHK(hipMemcpyAsync((void *)K.relax, P.code.data(), sizeof(u32) * P.code.size(), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync((void *)K.rw, P.wconst.data(), sizeof(u32) * P.code.size(), hipMemcpyHostToDevice, stream));
+    }
+
+    // pick the kernel
+    bool use_jit = false;
+    if (tc.jit == 1) use_jit = true;
+    else if (tc.jit == 2) use_jit = (rq.c_hi - rq.c_lo) >= (1ull << 32) || (P.N > 32 && (rq.c_hi - rq.c_lo) >= (1ull << 22));
+    hipFunction_t jfn = nullptr;
+    double jit_ms = 0.0;
+    if (use_jit) {
+        int rc = jit_get(D, P, rq.grad, jfn, jit_ms);
+        if (rc) return rc;
+    }
+
+    int rc = events_ready();
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(t_state.ev[0], stream));
+    HIPCHK(batk::build_tables(stream, rq.p_dev, m, f, (double *)K.tables, (int *)K.status));
+    HIPCHK(hipEventRecord(t_state.ev[1], stream));
+    const u64 blocks = (K.n_chunks + bat::kWavesPerBlock - 1) / bat::kWavesPerBlock;
+    if (blocks > 0x7fffffffull) return fail(BAT_ETOOBIG, "too many work items (%llu)", (unsigned long long)blocks);
+    if (use_jit) {
+        void *args[] = {&K};
+        HIPCHK(hipModuleLaunchKernel(jfn, (unsigned)blocks, 1, 1, bat::kBlock, 1, 1, 0, stream, args, nullptr));
+    } else {
+        HIPCHK(batk::sweep_dyn(stream, (unsigned)blocks, rq.grad, P.N, K));
+    }
+    HIPCHK(hipEventRecord(t_state.ev[2], stream));
+    HIPCHK(batk::reduce(stream, (const double *)K.part, (const u64 *)K.pcount, K.n_chunks, K.ncol, L.res, L.count));
+    HIPCHK(hipEventRecord(t_state.ev[3], stream));
+
+    bat_launch_info &I = t_state.info;
+    memset(&I, 0, sizeof I);
+    I.jit_ms = jit_ms;
+    I.vectors = rq.c_hi - rq.c_lo;
+    I.specialised = use_jit ? 1 : 0;
+    I.chunk_log2 = clog;
+    I.n_chunks = (int32_t)std::min<u64>(K.n_chunks, 0x7fffffff);
+    I.relaxations = (int32_t)P.code.size();
+    t_state.have_launch = true;
+    return BAT_OK;
+}
+
+struct Prepared {
+    DeviceInfo D;
+    Plan P;
+    hipStream_t stream = nullptr;
+};
+
+int prepare(int32_t n, int32_t m, const bat_arc *arcs, const double *p_host, int32_t s, int32_t t,
+            Prepared &X)
+{
+    int rc = validate(n, m, arcs, p_host, s, t);
+    if (rc) return rc;
+    rc = current_device(X.D);
+    if (rc) return rc;
+    make_plan(n, m, arcs, s, t, X.P);
+    return BAT_OK;
+}
+
+// Synchronous driver over host p; fills res (ncol doubles pairs) and count.
+int run_sync(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t, u64 c_lo,
+             u64 c_hi, bool grad, std::vector<double> &res, u64 &count, Request *tmpl = nullptr)
+{
+    Prepared X;
+    int rc = prepare(n, m, arcs, p, s, t, X);
+    if (rc) return rc;
+    if (!p && m > 0) return fail(BAT_EINVAL, "p is NULL");
+    rc = thread_stream(X.D.id, X.stream);
+    if (rc) return rc;
+    double *p_dev = nullptr;
+    HIPCHK(hipMallocAsync((void **)&p_dev, sizeof(double) * (m + 1), X.stream));
+    if (m > 0) HIPCHK(hipMemcpyAsync(p_dev, p, sizeof(double) * m, hipMemcpyHostToDevice, X.stream));
+    Request rq = tmpl ? *tmpl : Request{};
+    rq.n = n; rq.m = m; rq.s = s; rq.t = t; rq.arcs = arcs; rq.p_dev = p_dev;
+    rq.c_lo = c_lo; rq.c_hi = c_hi; rq.grad = grad;
+    Launch L;
+    rc = queue_sweep(rq, X.P, X.D, X.stream, L);
+    if (rc) {
+        (void)hipFreeAsync(p_dev, X.stream);
+        if (L.ws) (void)hipFreeAsync(L.ws, X.stream);
+        (void)hipStreamSynchronize(X.stream);
+        return rc;
+    }
+    res.assign(2 * L.ncol, 0.0);
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(res.data(), L.res, sizeof(double) * 2 * L.ncol, hipMemcpyDeviceToHost, X.stream));
+    HIPCHK(hipMemcpyAsync(&count, L.count, sizeof(u64), hipMemcpyDeviceToHost, X.stream));
+    HIPCHK(hipMemcpyAsync(&st, L.status, sizeof(int), hipMemcpyDeviceToHost, X.stream));
+    HIPCHK(hipFreeAsync(L.ws, X.stream));
+    HIPCHK(hipFreeAsync(p_dev, X.stream));
+    HIPCHK(hipStreamSynchronize(X.stream));
+    if (st) return fail(BAT_EINVAL, "a probability is outside [0,1]");
+    return BAT_OK;
+}
+
+void split_grad(const std::vector<double> &res, int32_t m, double *dRdp, double *T1, double *T0)
+{
+    for (int32_t a = 0; a < m; ++a) {
+        int cb = m - 1 - a;
+        const double *t0 = &res[2 * (1 + 2 * cb)], *t1 = &res[2 * (1 + 2 * cb + 1)];
+        if (dRdp) dRdp[a] = (t1[0] - t0[0]) + (t1[1] - t0[1]);
+        if (T1) T1[a] = t1[0] + t1[1];
+        if (T0) T0[a] = t0[0] + t0[1];
+    }
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *bat_version(void) { return kVersion; }
+
+const char *bat_last_error(void) { return t_err.c_str(); }
+
+int bat_set_option(const char *key, int64_t value)
+{
+    auto *o = opts().find(key);
+    if (!o) return fail(BAT_EINVAL, "unknown option '%s'", key ? key : "(null)");
+    *o = value;
+    return BAT_OK;
+}
+
+int bat_get_option(const char *key, int64_t *value)
+{
+    auto *o = opts().find(key);
+    if (!o || !value) return fail(BAT_EINVAL, "unknown option '%s'", key ? key : "(null)");
+    *value = o->load();
+    return BAT_OK;
+}
+
+int bat_reliability(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                    double *R_out, uint64_t *count_out)
+{
+    t_err.clear();
+    if (!R_out || !count_out) return fail(BAT_EINVAL, "NULL output pointer");
+    if (m < 0 || m > BAT_MAX_ARCS) return validate(n, m, arcs, p, s, t);
+    std::vector<double> res;
+    u64 cnt = 0;
+    int rc = run_sync(n, m, arcs, p, s, t, 0, 1ull << m, false, res, cnt);
+    if (rc) return rc;
+    *R_out = res[0] + res[1];
+    *count_out = cnt;
+    return BAT_OK;
+}
+
+int bat_reliability_grad(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                         double *R_out, uint64_t *count_out, double *dRdp_out, double *T1_out, double *T0_out)
+{
+    t_err.clear();
+    if (!R_out || !count_out || (!dRdp_out && m > 0)) return fail(BAT_EINVAL, "NULL output pointer");
+    if (m < 0 || m > BAT_MAX_ARCS) return validate(n, m, arcs, p, s, t);
+    std::vector<double> res;
+    u64 cnt = 0;
+    int rc = run_sync(n, m, arcs, p, s, t, 0, 1ull << m, true, res, cnt);
+    if (rc) return rc;
+    *R_out = res[0] + res[1];
+    *count_out = cnt;
+    split_grad(res, m, dRdp_out, T1_out, T0_out);
+    return BAT_OK;
+}
+
+int bat_reliability_range(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                          uint64_t c_lo, uint64_t c_hi, double *R_hi, double *R_lo, uint64_t *count_out,
+                          double *T1_out, double *T0_out)
+{
+    t_err.clear();
+    if (!R_hi || !R_lo || !count_out) return fail(BAT_EINVAL, "NULL output pointer");
+    if ((T1_out == nullptr) != (T0_out == nullptr)) return fail(BAT_EINVAL, "T1_out and T0_out must both be set or both NULL");
+    if (m < 0 || m > BAT_MAX_ARCS) return validate(n, m, arcs, p, s, t);
+    if (c_lo > c_hi || c_hi > (1ull << m)) return fail(BAT_EINVAL, "bad range [%llu, %llu) for m = %d",
+                                                     (unsigned long long)c_lo, (unsigned long long)c_hi, m);
+    bool grad = T1_out != nullptr;
+    if (c_lo == c_hi) {
+        int rc = validate(n, m, arcs, p, s, t);
+        if (rc) return rc;
+        *R_hi = *R_lo = 0.0;
+        *count_out = 0;
+        if (grad)
+            for (int32_t a = 0; a < m; ++a) T1_out[a] = T0_out[a] = 0.0;
+        return BAT_OK;
+    }
+    std::vector<double> res;
+    u64 cnt = 0;
+    int rc = run_sync(n, m, arcs, p, s, t, c_lo, c_hi, grad, res, cnt);
+    if (rc) return rc;
+    *R_hi = res[0];
+    *R_lo = res[1];
+    *count_out = cnt;
+    if (grad) split_grad(res, m, nullptr, T1_out, T0_out);
+    return BAT_OK;
+}
+
+static int async_common(int32_t n, int32_t m, const bat_arc *arcs, const double *p_dev, int32_t s, int32_t t,
+                        double *R_dev, uint64_t *count_dev, bool grad, double *dRdp_dev, double *T1_dev,
+                        double *T0_dev, int32_t *status_dev, void *stream)
+{
+    t_err.clear();
+    if (!R_dev || !count_dev || (grad && !dRdp_dev && m > 0)) return fail(BAT_EINVAL, "NULL output pointer");
+    if (m > 0 && !p_dev) return fail(BAT_EINVAL, "p_dev is NULL");
+    Prepared X;
+    int rc = prepare(n, m, arcs, nullptr, s, t, X);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Request rq{};
+    rq.n = n; rq.m = m; rq.s = s; rq.t = t; rq.arcs = arcs; rq.p_dev = p_dev;
+    rq.c_lo = 0; rq.c_hi = 1ull << m; rq.grad = grad;
+    Launch L;
+    rc = queue_sweep(rq, X.P, X.D, st, L);
+    if (rc) {
+        if (L.ws) (void)hipFreeAsync(L.ws, st);
+        return rc;
+    }
+    HIPCHK(batk::finalize(st, (const double *)L.res, (const u64 *)L.count, (const int *)L.status, (u32)m, grad,
+                          R_dev, (u64 *)count_dev, dRdp_dev, T1_dev, T0_dev, (int *)status_dev));
+    HIPCHK(hipFreeAsync(L.ws, st));
+    return BAT_OK;
+}
+
+int bat_reliability_async(int32_t n, int32_t m, const bat_arc *arcs, const double *p_dev, int32_t s, int32_t t,
+                          double *R_dev, uint64_t *count_dev, int32_t *status_dev, void *stream)
+{
+    return async_common(n, m, arcs, p_dev, s, t, R_dev, count_dev, false, nullptr, nullptr, nullptr, status_dev,
+                        stream);
+}
+
+int bat_reliability_grad_async(int32_t n, int32_t m, const bat_arc *arcs, const double *p_dev, int32_t s,
+                               int32_t t, double *R_dev, uint64_t *count_dev, double *dRdp_dev, double *T1_dev,
+                               double *T0_dev, int32_t *status_dev, void *stream)
+{
+    return async_common(n, m, arcs, p_dev, s, t, R_dev, count_dev, true, dRdp_dev, T1_dev, T0_dev, status_dev,
+                        stream);
+}
+
+int bat_last_launch(bat_launch_info *info)
+{
+    if (!info) return fail(BAT_EINVAL, "NULL info");
+    if (!t_state.have_launch) return fail(BAT_EINVAL, "no launch on this thread yet");
+    HIPCHK(hipEventSynchronize(t_state.ev[3]));
+    float k = 0.f, tot = 0.f;
+    HIPCHK(hipEventElapsedTime(&k, t_state.ev[1], t_state.ev[2]));
+    HIPCHK(hipEventElapsedTime(&tot, t_state.ev[0], t_state.ev[3]));
+    t_state.info.kernel_ms = k;
+    t_state.info.total_ms = tot;
+    *info = t_state.info;
+    return BAT_OK;
+}
+
+int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                 double *best_ns_per_vector)
+{
+    t_err.clear();
+    Prepared X;
+    int rc = prepare(n, m, arcs, p, s, t, X);
+    if (rc) return rc;
+    if (!p && m > 0) return fail(BAT_EINVAL, "p is NULL");
+    // sample: 8 ranges spread evenly over the counter, ~2^31 vectors in all
+    const u64 total = 1ull << m;
+    const int nslice = total >= (1ull << 16) ? 8 : 1;
+    const u64 want = std::min<u64>(total, 1ull << 31);
+    const u64 len = std::max<u64>(want / nslice, 1);
+    std::vector<std::pair<u64, u64>> ranges;
+    for (int i = 0; i < nslice; ++i) {
+        u64 lo = (total / nslice) * i;
+        ranges.push_back({lo, std::min(total, lo + len)});
+    }
+    struct Cand { int clog, check, jit; };
+    std::vector<Cand> cands;
+    for (int jit : {0, 1})
+        for (int check : {1, 2})
+            for (int clog : {8, 10, 12}) cands.push_back({clog, check, jit});
+    double best = 1e300;
+    Cand bc{0, 1, 2};
+    for (const Cand &c : cands) {
+        double ms = 0.0;
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {  // first pass warms the JIT cache
+            ms = 0.0;
+            for (auto &r : ranges) {
+                Request tmpl{};
+                tmpl.force_chunk_log2 = c.clog;
+                tmpl.force_check = c.check;
+                tmpl.force_jit = c.jit;
+                std::vector<double> res;
+                u64 cnt = 0;
+                if (run_sync(n, m, arcs, p, s, t, r.first, r.second, false, res, cnt, &tmpl)) {
+                    ok = false;
+                    break;
+                }
+                bat_launch_info li;
+                if (bat_last_launch(&li)) { ok = false; break; }
+                ms += li.kernel_ms;
+            }
+        }
+        if (ok && ms < best) {
+            best = ms;
+            bc = c;
+        }
+    }
+    u64 sampled = 0;
+    for (auto &r : ranges) sampled += r.second - r.first;
+    if (best_ns_per_vector) *best_ns_per_vector = best * 1e6 / (double)sampled;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        TuneChoice tc{bc.clog, bc.check, bc.jit};
+        g_tune[std::to_string(X.D.id) + " fwd " + X.P.structure] = tc;
+        g_tune[std::to_string(X.D.id) + " grad " + X.P.structure] = tc;
+    }
+    t_err.clear();
+    return BAT_OK;
+}
+
+}  // extern "C"
+
+extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_offsets,
+                                       const bat_arc *arcs, const int32_t *s, const int32_t *t, int32_t n_pvec,
+                                       const double *p, double *R_out, uint64_t *counts_out)
+{
+    (void)n_graphs; (void)n_nodes; (void)arc_offsets; (void)arcs; (void)s; (void)t;
+    (void)n_pvec; (void)p; (void)R_out; (void)counts_out;
+    return fail(BAT_EDEVICE, "batched kernel not built yet");
+}

@@ -1,0 +1,368 @@
+"""GPU parity: the HIP library against the CPU oracle (and the frontier DP).
+
+Bars (from the benchmark's tolerance for the sum of up to 2^40 FP64 terms):
+feasible counts bit-exact; R within 1e-12 relative; T1_i and T0_i within
+1e-12 relative; dR/dp_i within 1e-12 (T1_i + T0_i) absolute.  Both kernel
+instantiations are covered: the generic one (graph read at run time) and the
+graph-specialised one (compiled with hiprtc).
+"""
+import contextlib
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import bat_workloads as W
+import oracle
+from oracle import frontier_dp, pbat
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+def _B():
+    import paper_2209_09711_amd as B
+    return B
+
+
+@contextlib.contextmanager
+def options(**kw):
+    B = _B()
+    old = {k: B.bat_get_option(k) for k in kw}
+    try:
+        for k, v in kw.items():
+            B.bat_set_option(k, v)
+        yield
+    finally:
+        for k, v in old.items():
+            B.bat_set_option(k, v)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_ok(got, want, rel=REL):
+    if want == 0.0:
+        return got == 0.0
+    return abs(got - want) <= rel * abs(want)
+
+
+KERNELS = [pytest.param(0, id="generic"), pytest.param(1, id="specialised")]
+
+
+# ---------------------------------------------------------------- paper pins
+
+@pytest.mark.parametrize("jit", KERNELS)
+@pytest.mark.parametrize("pv", [0.9, 0.5, 0.123, 1.0, 0.0])
+def test_bridge(jit, pv):
+    B = _B()
+    b = W.bridge(pv)
+    with options(BAT_JIT=jit):
+        R, cnt = B.bat_reliability(b.n, b.arcs, b.p, b.s, b.t)
+    assert cnt == 16
+    want = 2 * pv**2 + 2 * pv**3 - 5 * pv**4 + 2 * pv**5
+    assert abs(R - want) <= 1e-15
+
+
+@pytest.mark.parametrize("jit", KERNELS)
+def test_figure1_and_table4_divisions(jit):
+    B = _B()
+    f = W.figure1()
+    with options(BAT_JIT=jit):
+        R, cnt = B.bat_reliability(f.n, f.arcs, f.p, f.s, f.t)
+        assert cnt == 25 and abs(R - 0.960175722) <= 0.5e-9
+        assert rel_ok(R, 4800878611 / 5000000000, 1e-15)
+        want = pbat.run(f.n, f.arcs, f.p, f.s, f.t, 4, processes=1)
+        for i in range(1, 5):      # Eq. 6 divisions, chi = 4
+            lo, hi = pbat.division_bounds(6, 4, i)
+            r = B.bat_reliability_range(f.n, f.arcs, f.p, f.s, f.t, lo, hi)
+            assert r.count == want.division_count[i - 1]
+            assert rel_ok(r.R, want.division_R[i - 1])
+
+
+# ----------------------------------------------------------- random parity
+
+def _cases(k, seed, m_max=20, n_max=20):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(k):
+        kind = i % 4
+        if kind == 3:
+            n = int(rng.integers(2, 8))
+            m = int(rng.integers(0, 14))
+            net = W.random_multigraph(n, m, seed=int(rng.integers(1 << 30)), p_lo=0.0, p_hi=1.0)
+            if m:
+                net.p[rng.random(m) < 0.15] = 1.0
+                net.p[rng.random(m) < 0.15] = 0.0
+        else:
+            n = int(rng.integers(3, n_max + 1))
+            mmin, mmax = n - 1, min(m_max, n * (n - 1) // 2)
+            m = int(rng.integers(mmin, mmax + 1))
+            net = W.random_connected(n, m, seed=int(rng.integers(1 << 30)), p_lo=0.05, p_hi=0.99)
+        out.append(net)
+    return out
+
+
+@pytest.mark.parametrize("jit", KERNELS)
+def test_random_vs_oracle(jit):
+    B = _B()
+    nets = _cases(24 if jit == 0 else 10, 1234 + jit)
+    with options(BAT_JIT=jit):
+        for net in nets:
+            say("case", net.name, net.n, net.m, net.s, net.t)
+            R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+            o = oracle.net_reliability(net)
+            assert cnt == o.count, net.name
+            assert rel_ok(R, o.sum), (net.name, R, o.sum)
+
+
+@pytest.mark.parametrize("jit", KERNELS)
+@pytest.mark.parametrize("n", [16, 17, 33, 34])
+def test_node_count_classes(jit, n):
+    """A cycle of n nodes (every node relevant), s and t opposite: R is
+    1 - (1 - prod path1)(1 - prod path2) and the count is
+    2^n - (2^a - 1)(2^b - 1) for path lengths a, b."""
+    B = _B()
+    rng = np.random.default_rng(n)
+    arcs = [(i, (i + 1) % n) for i in range(n)]
+    p = rng.uniform(0.9, 0.999, n)
+    s, t = 0, n // 2
+    with options(BAT_JIT=jit):
+        say("cycle", n)
+        R, cnt = B.bat_reliability(n, arcs, p, s, t)
+    a, b = t, n - t
+    want = 1.0 - (1.0 - np.prod(p[:a])) * (1.0 - np.prod(p[a:]))
+    assert cnt == (1 << n) - ((1 << a) - 1) * ((1 << b) - 1)
+    assert rel_ok(R, want, 1e-13)
+
+
+@pytest.mark.parametrize("jit", KERNELS)
+def test_edge_cases(jit):
+    B = _B()
+    with options(BAT_JIT=jit):
+        # m = 0: one empty vector, disconnected
+        R, cnt = B.bat_reliability(2, np.zeros((0, 2), np.int32), np.zeros(0), 0, 1)
+        assert R == 0.0 and cnt == 0
+        # s and t in different components
+        R, cnt = B.bat_reliability(4, [(0, 1), (2, 3)], [0.9, 0.9], 0, 3)
+        assert R == 0.0 and cnt == 0
+        # only self-loops and a parallel pair
+        arcs = [(0, 0), (0, 1), (0, 1), (1, 1)]
+        p = [0.3, 0.6, 0.7, 0.9]
+        R, cnt = B.bat_reliability(2, arcs, p, 0, 1)
+        assert cnt == 12 and abs(R - (1 - 0.4 * 0.3)) <= 1e-15
+        # m = 11 and 12: exactly one word/wave, and one iteration bit
+        for m in (5, 10, 11, 12):
+            net = W.random_connected(8, m, seed=m, p_lo=0.1, p_hi=0.9)
+            R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+            o = oracle.net_reliability(net)
+            assert cnt == o.count and rel_ok(R, o.sum)
+
+
+# ------------------------------------------------------ full-size workloads
+
+def test_config1_full_vs_frontier_dp():
+    B = _B()
+    c = W.config1()
+    say("config1", c.n, c.m)
+    R, cnt = B.bat_reliability(c.n, c.arcs, c.p, c.s, c.t)
+    Rd, cd = frontier_dp.reliability(c.n, c.arcs, c.p, c.s, c.t)
+    assert cnt == cd and rel_ok(R, Rd)
+    # sampled divisions against the BAT oracle, spread over the counter
+    chi = 1 << 10
+    for i in pbat.spread_divisions(chi, 3):
+        lo, hi = pbat.division_bounds(c.m, chi, i)
+        r = B.bat_reliability_range(c.n, c.arcs, c.p, c.s, c.t, lo, hi)
+        o = oracle.reliability_range(c.n, c.arcs, c.p, c.s, c.t, lo, hi)
+        assert r.count == o.count and rel_ok(r.R, o.sum)
+
+
+def test_config2_grid_full_vs_frontier_dp():
+    """The headline workload (2^40 vectors) in the launch shape bench.py times."""
+    B = _B()
+    c = W.config2()
+    say("config2", c.n, c.m)
+    R, cnt = B.bat_reliability(c.n, c.arcs, c.p, c.s, c.t)
+    info = B.bat_last_launch()
+    say("config2 kernel ms", info.kernel_ms, "specialised", info.specialised)
+    Rd, cd = frontier_dp.reliability(c.n, c.arcs, c.p, c.s, c.t)
+    assert cnt == cd and rel_ok(R, Rd)
+    # ragged sampled ranges against the oracle
+    rng = np.random.default_rng(2)
+    for _ in range(3):
+        lo = int(rng.integers(0, (1 << 40) - (1 << 21)))
+        hi = lo + int(rng.integers(1 << 19, 1 << 20))
+        r = B.bat_reliability_range(c.n, c.arcs, c.p, c.s, c.t, lo, hi)
+        o = oracle.reliability_range(c.n, c.arcs, c.p, c.s, c.t, lo, hi)
+        assert r.count == o.count and rel_ok(r.R, o.sum)
+
+
+def test_config4_grad_full_vs_frontier_dp():
+    B = _B()
+    c = W.config4()
+    say("config4", c.n, c.m)
+    g = B.bat_reliability_grad(c.n, c.arcs, c.p, c.s, c.t)
+    Rd, cd = frontier_dp.reliability(c.n, c.arcs, c.p, c.s, c.t)
+    assert g.count == cd and rel_ok(g.R, Rd)
+    T1, T0 = frontier_dp.gradient(c.n, c.arcs, c.p, c.s, c.t)
+    for i in range(c.m):
+        assert rel_ok(g.T1[i], T1[i]), (i, g.T1[i], T1[i])
+        assert rel_ok(g.T0[i], T0[i]), (i, g.T0[i], T0[i])
+        assert abs(g.dRdp[i] - (T1[i] - T0[i])) <= REL * (T1[i] + T0[i])
+    # the forward-only sweep agrees with the forward+gradient sweep
+    R, cnt = B.bat_reliability(c.n, c.arcs, c.p, c.s, c.t)
+    assert cnt == g.count and rel_ok(R, g.R)
+    # central finite differences (exact up to rounding: R is multilinear)
+    h = 1e-6
+    for i in (0, 7, 35):
+        q = c.p.copy(); q[i] += h
+        Rp, _ = B.bat_reliability(c.n, c.arcs, q, c.s, c.t)
+        q[i] -= 2 * h
+        Rm, _ = B.bat_reliability(c.n, c.arcs, q, c.s, c.t)
+        assert abs((Rp - Rm) / (2 * h) - g.dRdp[i]) <= 1e-9
+
+
+# ---------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("jit", KERNELS)
+def test_half_probability_bit_exact(jit):
+    B = _B()
+    with options(BAT_JIT=jit):
+        for seed in range(3):
+            net = W.random_connected(14, 24 + seed, seed=seed)
+            R, cnt = B.bat_reliability(net.n, net.arcs, np.full(net.m, 0.5), net.s, net.t)
+            assert R == cnt * 2.0 ** -net.m
+            o = oracle.net_reliability(net, p=np.full(net.m, 0.5))
+            assert cnt == o.count
+
+
+def test_p_one_zero_and_complement():
+    B = _B()
+    net = W.random_connected(12, 20, seed=9)
+    R1, c1 = B.bat_reliability(net.n, net.arcs, np.ones(net.m), net.s, net.t)
+    R0, c0 = B.bat_reliability(net.n, net.arcs, np.zeros(net.m), net.s, net.t)
+    assert R1 == 1.0 and R0 == 0.0 and c1 == c0
+
+
+def test_determinism_and_launch_variants():
+    B = _B()
+    net = W.random_connected(16, 26, seed=77, p_lo=0.6, p_hi=0.99)
+    base = [B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t) for _ in range(10)]
+    assert all(b == base[0] for b in base)          # bitwise
+    R0, c0 = base[0]
+    for jit in (0, 1):
+        for check in (1, 2):
+            for clog in (1, 4, 9):
+                with options(BAT_JIT=jit, BAT_CHECK_EVERY=check, BAT_CHUNK_LOG2=clog):
+                    R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+                assert cnt == c0 and rel_ok(R, R0), (jit, check, clog)
+    for seg in (0, 3, 8):
+        with options(BAT_SEG_LOG2=seg):
+            g = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+        assert g.count == c0 and rel_ok(g.R, R0)
+
+
+def test_arc_permutation_invariance():
+    B = _B()
+    net = W.random_connected(15, 24, seed=5, p_lo=0.3, p_hi=0.97)
+    R0, c0 = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        perm = rng.permutation(net.m)
+        arcs = [net.arcs[i] for i in perm]
+        R, cnt = B.bat_reliability(net.n, arcs, net.p[perm], net.s, net.t)
+        assert cnt == c0 and rel_ok(R, R0)
+
+
+# ------------------------------------------------------------------ gradient
+
+@pytest.mark.parametrize("jit", KERNELS)
+def test_grad_vs_oracle(jit):
+    B = _B()
+    nets = _cases(12 if jit == 0 else 6, 99 + jit, m_max=18, n_max=14)
+    nets.append(W.bridge(0.9).with_p([1.0, 0.0, 0.7, 1.0, 0.0]))
+    with options(BAT_JIT=jit):
+        for net in nets:
+            say("grad case", net.name, net.n, net.m)
+            g = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+            o = oracle.net_reliability(net, grad=True)
+            assert g.count == o.count and rel_ok(g.R, o.sum)
+            for i in range(net.m):
+                assert rel_ok(g.T1[i], o.T1[i]), (net.name, i, g.T1[i], o.T1[i])
+                assert rel_ok(g.T0[i], o.T0[i]), (net.name, i, g.T0[i], o.T0[i])
+                assert abs(g.dRdp[i] - (o.T1[i] - o.T0[i])) <= REL * (o.T1[i] + o.T0[i]) + 1e-300
+
+
+def test_grad_birnbaum_bruteforce():
+    B = _B()
+    net = W.random_connected(13, 22, seed=4, p_lo=0.5, p_hi=0.95)
+    g = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+    for i in range(net.m):
+        q = net.p.copy(); q[i] = 1.0
+        R1, _ = B.bat_reliability(net.n, net.arcs, q, net.s, net.t)
+        q[i] = 0.0
+        R0, _ = B.bat_reliability(net.n, net.arcs, q, net.s, net.t)
+        assert abs(g.dRdp[i] - (R1 - R0)) <= 1e-13
+        assert g.dRdp[i] >= -1e-15
+
+
+# --------------------------------------------------------------- range API
+
+def test_ranges_compose():
+    B = _B()
+    net = W.random_connected(14, 27, seed=31, p_lo=0.4, p_hi=0.99)
+    full = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+    cuts = [0, 1, 2047, 2048, 70001, 1 << 20, (1 << 27) - 5, 1 << 27]
+    hi = lo = 0.0
+    cnt = 0
+    T1 = np.zeros(net.m)
+    T0 = np.zeros(net.m)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        r = B.bat_reliability_range(net.n, net.arcs, net.p, net.s, net.t, a, b, grad=True)
+        o = oracle.reliability_range(net.n, net.arcs, net.p, net.s, net.t, a, b) if b - a < (1 << 21) else None
+        if o is not None:
+            assert r.count == o.count and rel_ok(r.R, o.sum)
+        hi, lo = pbat.dd_add(hi, lo, r.R_hi, r.R_lo)
+        cnt += r.count
+        T1 += r.T1
+        T0 += r.T0
+    assert cnt == full.count and rel_ok(hi + lo, full.R)
+    assert np.allclose(T1, full.T1, rtol=1e-12, atol=0) and np.allclose(T0, full.T0, rtol=1e-12, atol=0)
+
+
+# ------------------------------------------------------------------- torch
+
+def test_torch_autograd_and_async():
+    import torch
+    from paper_2209_09711_amd.torch_fn import reliability
+    B = _B()
+    net = W.random_connected(10, 16, seed=12, p_lo=0.3, p_hi=0.95)
+    p = torch.tensor(net.p, dtype=torch.float64, device="cuda", requires_grad=True)
+    R, cnt = reliability(p, net.n, net.arcs, net.s, net.t)
+    R.backward()
+    g = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+    assert R.item() == g.R and int(cnt.item()) == g.count
+    assert np.array_equal(p.grad.cpu().numpy(), g.dRdp)
+    q = torch.tensor(net.p[:8] * 0 + 0.6, dtype=torch.float64, device="cuda", requires_grad=True)
+    small = W.random_connected(6, 8, seed=3)
+    fn = lambda x: reliability(x, small.n, small.arcs, small.s, small.t)[0]
+    assert torch.autograd.gradcheck(fn, (q,), eps=1e-6, atol=1e-9, rtol=1e-7)
+
+
+def test_async_invalid_probability():
+    import torch
+    B = _B()
+    net = W.random_connected(6, 8, seed=3)
+    p = torch.tensor(net.p, dtype=torch.float64, device="cuda")
+    p[2] = 1.5
+    R = torch.zeros((), dtype=torch.float64, device="cuda")
+    cnt = torch.zeros((), dtype=torch.int64, device="cuda")
+    st = torch.zeros((), dtype=torch.int32, device="cuda")
+    B.bat_reliability_async(net.n, net.arcs, p.data_ptr(), net.s, net.t, R.data_ptr(), cnt.data_ptr(),
+                            st.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert int(st.item()) == B.BAT_EINVAL and np.isnan(R.item())
