@@ -108,10 +108,13 @@ int bat_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, 
  * p holds, graph after graph, an n_pvec x m_g row-major block (arc fastest),
  * i.e. graph g's block starts at n_pvec * arc_offsets[g].  One connectivity
  * verdict per state vector serves all n_pvec probability vectors of its
- * graph.  Outputs: R_out[g * n_pvec + j] and counts_out[g].  Limits per
- * graph as above; 1 <= n_pvec <= BAT_MAX_PVEC.
+ * graph (in groups of up to 32 per pass over the graph's vectors).  Work
+ * items (graph, counter range) are queued largest graph first and taken by
+ * one persistent block per compute unit.  Outputs: R_out[g * n_pvec + j]
+ * and counts_out[g], host pointers.  Limits per graph as above;
+ * 1 <= n_pvec <= BAT_MAX_PVEC.  Blocks until done.
  */
-#define BAT_MAX_PVEC 64
+#define BAT_MAX_PVEC 1024
 int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_offsets,
                             const bat_arc *arcs, const int32_t *s, const int32_t *t,
                             int32_t n_pvec, const double *p, double *R_out, uint64_t *counts_out);

@@ -25,7 +25,7 @@ BAT_EDEVICE = -3
 BAT_ENOMEM = -4
 BAT_MAX_NODES = 64
 BAT_MAX_ARCS = 62
-BAT_MAX_PVEC = 64
+BAT_MAX_PVEC = 1024
 
 # Every entry point of include/bat.h.
 EXPORTED = ("bat_version", "bat_last_error", "bat_reliability", "bat_reliability_grad",

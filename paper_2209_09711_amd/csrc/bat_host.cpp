@@ -800,7 +800,161 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
                                        const bat_arc *arcs, const int32_t *s, const int32_t *t, int32_t n_pvec,
                                        const double *p, double *R_out, uint64_t *counts_out)
 {
-    (void)n_graphs; (void)n_nodes; (void)arc_offsets; (void)arcs; (void)s; (void)t;
-    (void)n_pvec; (void)p; (void)R_out; (void)counts_out;
-    return fail(BAT_EDEVICE, "batched kernel not built yet");
+    t_err.clear();
+    if (n_graphs <= 0) return fail(BAT_EINVAL, "n_graphs must be >= 1");
+    if (!n_nodes || !arc_offsets || !s || !t || !R_out || !counts_out) return fail(BAT_EINVAL, "NULL argument");
+    if (n_pvec < 1 || n_pvec > BAT_MAX_PVEC) return fail(BAT_EINVAL, "n_pvec %d outside [1, %d]", n_pvec, BAT_MAX_PVEC);
+    if (arc_offsets[0] != 0) return fail(BAT_EINVAL, "arc_offsets[0] must be 0");
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        int32_t m = arc_offsets[g + 1] - arc_offsets[g];
+        if (m < 0) return fail(BAT_EINVAL, "arc_offsets not ascending at graph %d", g);
+        int rc = validate(n_nodes[g], m, m ? arcs + arc_offsets[g] : nullptr, nullptr, s[g], t[g]);
+        if (rc) return fail(rc, "graph %d: %s", g, t_err.c_str());
+        if (m > 0 && !p) return fail(BAT_EINVAL, "p is NULL");
+        const double *pg = p + (int64_t)n_pvec * arc_offsets[g];
+        for (int64_t i = 0; i < (int64_t)n_pvec * m; ++i)
+            if (!(pg[i] >= 0.0 && pg[i] <= 1.0))
+                return fail(BAT_EINVAL, "graph %d: p[%lld] = %g is not a probability", g, (long long)i, pg[i]);
+    }
+    DeviceInfo D;
+    int rc = current_device(D);
+    if (rc) return rc;
+    hipStream_t st;
+    rc = thread_stream(D.id, st);
+    if (rc) return rc;
+
+    // plans, entries (graph x group of <= 32 p-vectors), longest first
+    std::vector<Plan> plans(n_graphs);
+    std::vector<u32> codes, rws;
+    std::vector<u32> relax_off(n_graphs);
+    int nmax = 2;
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        int32_t m = arc_offsets[g + 1] - arc_offsets[g];
+        make_plan(n_nodes[g], m, arcs + arc_offsets[g], s[g], t[g], plans[g]);
+        relax_off[g] = (u32)codes.size();
+        codes.insert(codes.end(), plans[g].code.begin(), plans[g].code.end());
+        rws.insert(rws.end(), plans[g].wconst.begin(), plans[g].wconst.end());
+        nmax = std::max(nmax, plans[g].N);
+    }
+    std::vector<batk::BatchEntry> ents;
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        const Plan &P = plans[g];
+        u32 m = (u32)P.m;
+        u32 ubits = m > (u32)bat::kWordBits ? m - bat::kWordBits : 0u;
+        for (int32_t b = 0; b < n_pvec; b += batk::kBatchMaxP) {
+            batk::BatchEntry e;
+            memset(&e, 0, sizeof e);
+            e.m = m;
+            e.ubits = ubits;
+            e.f = std::min<u32>(ubits, batk::kBatchSegLog);
+            e.P = (u32)std::min<int32_t>(batk::kBatchMaxP, n_pvec - b);
+            e.n_nodes = (u32)P.N;
+            e.s = (u32)P.S;
+            e.t = (u32)P.T;
+            e.n_relax = (u32)P.code.size();
+            e.relax_off = relax_off[g];
+            e.graph = (u32)g;
+            e.pv_base = (u32)b;
+            ents.push_back(e);
+        }
+    }
+    std::stable_sort(ents.begin(), ents.end(),
+                     [](const batk::BatchEntry &a, const batk::BatchEntry &b) { return a.m > b.m; });
+    u64 n_items = 0, tab = 0;
+    std::vector<u64> item_start;
+    std::vector<u32> pair_entry, pair_pv;
+    std::vector<u64> entry_p_off;
+    u64 vectors = 0;
+    for (size_t i = 0; i < ents.size(); ++i) {
+        batk::BatchEntry &e = ents[i];
+        u64 iters = 1ull << e.ubits;
+        u64 per_item = (u64)batk::kBatchWaves << e.f;
+        e.item_begin = n_items;
+        e.n_items = (iters + per_item - 1) / per_item;
+        e.tab_off = tab;
+        item_start.push_back(n_items);
+        n_items += e.n_items;
+        tab += (u64)e.P * bat::kTablesFwd;
+        for (u32 q = 0; q < e.P; ++q) {
+            pair_entry.push_back((u32)i);
+            pair_pv.push_back(q);
+        }
+        entry_p_off.push_back((u64)n_pvec * (u64)arc_offsets[e.graph]);
+        vectors += 1ull << e.m;
+    }
+    item_start.push_back(n_items);
+    const int64_t p_total = (int64_t)n_pvec * arc_offsets[n_graphs];
+
+    // device buffers (one stream-ordered allocation)
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+    const size_t o_ent = take(sizeof(batk::BatchEntry) * ents.size());
+    const size_t o_ist = take(sizeof(u64) * item_start.size());
+    const size_t o_code = take(sizeof(u32) * (codes.size() + 1));
+    const size_t o_rw = take(sizeof(u32) * (codes.size() + 1));
+    const size_t o_pe = take(sizeof(u32) * pair_entry.size());
+    const size_t o_pp = take(sizeof(u32) * pair_pv.size());
+    const size_t o_epo = take(sizeof(u64) * entry_p_off.size());
+    const size_t o_p = take(sizeof(double) * (size_t)(p_total + 1));
+    const size_t o_tab = take(sizeof(double) * tab);
+    const size_t o_part = take(sizeof(double) * 2 * batk::kBatchMaxP * n_items);
+    const size_t o_pc = take(sizeof(u64) * n_items);
+    const size_t o_ctr = take(sizeof(unsigned long long));
+    const size_t o_R = take(sizeof(double) * (size_t)n_graphs * n_pvec);
+    const size_t o_cnt = take(sizeof(u64) * (size_t)n_graphs);
+    char *ws = nullptr;
+    HIPCHK(hipMallocAsync((void **)&ws, off, st));
+    auto h2d = [&](size_t o, const void *src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(ws + o, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+    };
+    HIPCHK(h2d(o_ent, ents.data(), sizeof(batk::BatchEntry) * ents.size()));
+    HIPCHK(h2d(o_ist, item_start.data(), sizeof(u64) * item_start.size()));
+    HIPCHK(h2d(o_code, codes.data(), sizeof(u32) * codes.size()));
+    HIPCHK(h2d(o_rw, rws.data(), sizeof(u32) * rws.size()));
+    HIPCHK(h2d(o_pe, pair_entry.data(), sizeof(u32) * pair_entry.size()));
+    HIPCHK(h2d(o_pp, pair_pv.data(), sizeof(u32) * pair_pv.size()));
+    HIPCHK(h2d(o_epo, entry_p_off.data(), sizeof(u64) * entry_p_off.size()));
+    HIPCHK(h2d(o_p, p, sizeof(double) * (size_t)p_total));
+    HIPCHK(hipMemsetAsync(ws + o_ctr, 0, sizeof(unsigned long long), st));
+
+    const batk::BatchEntry *d_ent = (const batk::BatchEntry *)(ws + o_ent);
+    rc = events_ready();
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(t_state.ev[0], st));
+    HIPCHK(batk::batched_tables(st, d_ent, (const u32 *)(ws + o_pe), (const u32 *)(ws + o_pp),
+                                (const u64 *)(ws + o_epo), (const double *)(ws + o_p), (unsigned)pair_entry.size(),
+                                (double *)(ws + o_tab)));
+    HIPCHK(hipEventRecord(t_state.ev[1], st));
+    batk::BatchParams BP;
+    memset(&BP, 0, sizeof BP);
+    BP.entries = d_ent;
+    BP.item_start = (const u64 *)(ws + o_ist);
+    BP.n_entries = (u32)ents.size();
+    BP.check_every = opts().check_every.load() >= 2 ? 2u : 1u;
+    BP.n_items = n_items;
+    BP.codes = (const u32 *)(ws + o_code);
+    BP.rw = (const u32 *)(ws + o_rw);
+    BP.tables = (const double *)(ws + o_tab);
+    BP.part = (double *)(ws + o_part);
+    BP.pcount = (u64 *)(ws + o_pc);
+    BP.ctr = (unsigned long long *)(ws + o_ctr);
+    unsigned blocks = (unsigned)std::max<u64>(1, std::min<u64>((u64)D.cus, n_items));
+    HIPCHK(batk::batched_sweep(st, blocks, nmax, BP));
+    HIPCHK(hipEventRecord(t_state.ev[2], st));
+    HIPCHK(batk::batched_reduce(st, d_ent, (unsigned)ents.size(), (const double *)(ws + o_part),
+                                (const u64 *)(ws + o_pc), (u32)n_pvec, (double *)(ws + o_R), (u64 *)(ws + o_cnt)));
+    HIPCHK(hipEventRecord(t_state.ev[3], st));
+    HIPCHK(hipMemcpyAsync(R_out, ws + o_R, sizeof(double) * (size_t)n_graphs * n_pvec, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(counts_out, ws + o_cnt, sizeof(u64) * (size_t)n_graphs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipFreeAsync(ws, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bat_launch_info &I = t_state.info;
+    memset(&I, 0, sizeof I);
+    I.vectors = vectors;
+    I.specialised = 0;
+    I.chunk_log2 = batk::kBatchSegLog;
+    I.n_chunks = (int32_t)std::min<u64>(n_items, 0x7fffffff);
+    I.relaxations = (int32_t)codes.size();
+    t_state.have_launch = true;
+    return BAT_OK;
 }

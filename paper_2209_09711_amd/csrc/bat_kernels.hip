@@ -27,17 +27,12 @@ __device__ __forceinline__ double qbit(const double *p, u32 m, u32 cb, u32 x)
 
 }  // namespace
 
-// One block of 256 threads.  Layout: see the k* offsets in bat_device.hpp.
-extern "C" __global__ void __launch_bounds__(256)
-k_build_tables(const double *__restrict__ p, u32 m, u32 f, double *__restrict__ T, int *status)
+// The probability tables of one p-vector (layout: the k* offsets in
+// bat_device.hpp), computed by one block.  grad = false skips the tables
+// only the gradient sweep reads.
+__device__ void build_tables_dev(const double *__restrict__ p, u32 m, u32 f, double *__restrict__ T, bool grad)
 {
     const u32 tid = threadIdx.x;
-    if (tid == 0) {
-        int st = 0;
-        for (u32 i = 0; i < m; ++i)
-            if (!(p[i] >= 0.0 && p[i] <= 1.0)) st = -1;
-        *status = st;
-    }
     const u32 ubits = m > (u32)bat::kWordBits ? m - bat::kWordBits : 0u;
     // B(i) over slice bits 0..2 and its one-bit-removed variants
     for (u32 y = tid; y < 256; y += blockDim.x) {
@@ -53,11 +48,12 @@ k_build_tables(const double *__restrict__ p, u32 m, u32 f, double *__restrict__ 
             sg[2 * 2 + ((i >> 2) & 1u)] += q0 * q1;
         }
         T[bat::kTB + y] = s;
-        for (u32 k = 0; k < 6; ++k) T[bat::kTBG + k * 256 + y] = sg[k];
         // Q_lo over iteration bits below f
         double ql = 1.0;
         for (u32 b = 0; b < f; ++b) ql *= qbit(p, m, bat::kWordBits + b, (y >> b) & 1u);
         T[bat::kQlo + y] = (y < (1u << f)) ? ql : 0.0;
+        if (!grad) continue;
+        for (u32 k = 0; k < 6; ++k) T[bat::kTBG + k * 256 + y] = sg[k];
         for (u32 b = 0; b < 8; ++b) {
             double qm = 1.0;
             for (u32 b2 = 0; b2 < f; ++b2)
@@ -67,24 +63,40 @@ k_build_tables(const double *__restrict__ p, u32 m, u32 f, double *__restrict__ 
     }
     if (tid < 4) {
         T[bat::kA4 + tid] = qbit(p, m, 3, tid & 1u) * qbit(p, m, 4, tid >> 1);
-        T[bat::kA4M + tid] = qbit(p, m, 4, tid >> 1);      // without slice bit 3
-        T[bat::kA4M + 4 + tid] = qbit(p, m, 3, tid & 1u);  // without slice bit 4
+        if (grad) {
+            T[bat::kA4M + tid] = qbit(p, m, 4, tid >> 1);      // without slice bit 3
+            T[bat::kA4M + 4 + tid] = qbit(p, m, 3, tid & 1u);  // without slice bit 4
+        }
     }
     if (tid < 64) {
         double q = 1.0;
         for (u32 b = 0; b < 6; ++b) q *= qbit(p, m, bat::kSliceBits + b, (tid >> b) & 1u);
         T[bat::kQL + tid] = q;
-        for (u32 b = 0; b < 6; ++b) {
-            double qm = 1.0;
-            for (u32 b2 = 0; b2 < 6; ++b2)
-                if (b2 != b) qm *= qbit(p, m, bat::kSliceBits + b2, (tid >> b2) & 1u);
-            T[bat::kQLM + b * 64 + tid] = qm;
-        }
+        if (grad)
+            for (u32 b = 0; b < 6; ++b) {
+                double qm = 1.0;
+                for (u32 b2 = 0; b2 < 6; ++b2)
+                    if (b2 != b) qm *= qbit(p, m, bat::kSliceBits + b2, (tid >> b2) & 1u);
+                T[bat::kQLM + b * 64 + tid] = qm;
+            }
     }
     if (tid < 128) {
         u32 b = tid >> 1, x = tid & 1u;
         T[bat::kQG + tid] = (b < ubits) ? qbit(p, m, bat::kWordBits + b, x) : (x ? 0.0 : 1.0);
     }
+}
+
+// One block of 256 threads for the single-graph sweeps; also checks p.
+extern "C" __global__ void __launch_bounds__(256)
+k_build_tables(const double *__restrict__ p, u32 m, u32 f, double *__restrict__ T, int *status)
+{
+    if (threadIdx.x == 0) {
+        int st = 0;
+        for (u32 i = 0; i < m; ++i)
+            if (!(p[i] >= 0.0 && p[i] <= 1.0)) st = -1;
+        *status = st;
+    }
+    build_tables_dev(p, m, f, T, true);
 }
 
 template <int NMAX>
@@ -173,6 +185,167 @@ k_finalize(const double *__restrict__ res, const u64 *__restrict__ count, const 
     }
 }
 
+// ------------------------------------------------------------ batched form
+// Tables of (entry, p-vector) pair k: one block per pair.
+extern "C" __global__ void __launch_bounds__(256)
+k_batched_tables(const batk::BatchEntry *__restrict__ entries, const u32 *__restrict__ pair_entry,
+                 const u32 *__restrict__ pair_pv, const u64 *__restrict__ entry_p_off, const double *__restrict__ p,
+                 double *__restrict__ tables)
+{
+    const u32 k = blockIdx.x;
+    const u32 e = pair_entry[k], pv = pair_pv[k];
+    const batk::BatchEntry E = entries[e];
+    build_tables_dev(p + entry_p_off[e] + (u64)(E.pv_base + pv) * E.m, E.m, E.f,
+                     tables + E.tab_off + (u64)pv * bat::kTablesFwd, false);
+}
+
+// Persistent: every block loops { take the next item from the queue; load
+// its entry's tables into LDS; each wavefront sweeps 2^f iterations of the
+// graph's counter and adds, for every probability vector, Q_lo * F(V) per
+// word (one connectivity verdict serves all of them); fold the wavefronts
+// in a fixed order into the item's own partial slot }.  Items are queued
+// longest graph first.  Every wavefront leaves when the queue is empty.
+template <int NMAX>
+__global__ void __launch_bounds__(batk::kBatchThreads) k_batched_dyn(batk::BatchParams B)
+{
+    using namespace batk;
+    __shared__ double tb[kBatchMaxP][256];
+    __shared__ double a4[kBatchMaxP][4];
+    __shared__ double qlo[kBatchMaxP][1 << kBatchSegLog];
+    __shared__ double wsum[kBatchWaves][kBatchMaxP][2];
+    __shared__ u64 wcnt[kBatchWaves];
+    __shared__ u64 s_item;
+    __shared__ u32 s_entry;
+    const u32 tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+    for (;;) {
+        if (tid == 0) {
+            u64 it = atomicAdd(B.ctr, 1ull);
+            u32 lo = 0, hi = B.n_entries;   // entry e with item_start[e] <= it < item_start[e+1]
+            while (hi - lo > 1) {
+                u32 mid = (lo + hi) >> 1;
+                if (B.item_start[mid] <= it) lo = mid;
+                else hi = mid;
+            }
+            s_item = it;
+            s_entry = lo;
+        }
+        __syncthreads();
+        const u64 item = s_item;
+        if (item >= B.n_items) break;
+        const BatchEntry E = B.entries[s_entry];
+        const u32 P = E.P, f = E.f;
+        const double *T = B.tables + E.tab_off;
+        for (u32 i = tid; i < P * 256u; i += kBatchThreads)
+            tb[i >> 8][i & 255u] = T[(u64)(i >> 8) * bat::kTablesFwd + bat::kTB + (i & 255u)];
+        for (u32 i = tid; i < P * 4u; i += kBatchThreads) a4[i >> 2][i & 3u] = T[(u64)(i >> 2) * bat::kTablesFwd + bat::kA4 + (i & 3u)];
+        for (u32 i = tid; i < (P << kBatchSegLog); i += kBatchThreads)
+            qlo[i >> kBatchSegLog][i & ((1u << kBatchSegLog) - 1u)] =
+                T[(u64)(i >> kBatchSegLog) * bat::kTablesFwd + bat::kQlo + (i & ((1u << kBatchSegLog) - 1u))];
+        __syncthreads();
+
+        const u64 iters = 1ull << E.ubits;
+        const u64 seg = (item - E.item_begin) * kBatchWaves + w;
+        const u64 g0 = seg << f;
+        double tot[kBatchMaxP];
+#pragma unroll
+        for (int q = 0; q < kBatchMaxP; ++q) tot[q] = 0.0;
+        u64 cnt = 0;
+        if (g0 < iters) {
+            u64 g1 = g0 + (1ull << f) - 1ull;
+            if (g1 > iters - 1) g1 = iters - 1;
+            bat::KParams K;
+            K.s = E.s;
+            K.t = E.t;
+            K.n_relax = E.n_relax;
+            K.relax = B.codes + E.relax_off;
+            K.rw = B.rw + E.relax_off;
+            K.check_every = B.check_every;
+            bat::DynClosure<NMAX> cl;
+            cl.init(lane, K);
+            const u64 chi = E.m >= 63 ? ~0ull : (1ull << E.m);
+            for (u64 g = g0; g <= g1; ++g) {
+                u32 V = cl.verdict(g, K);
+                if (g == iters - 1) V &= bat::edge_mask(0ull, chi, g, lane);
+                cnt += __popc(V);
+                if (__ballot(V != 0u) == 0ull) continue;
+                const u32 b0 = V & 255u, b1 = (V >> 8) & 255u, b2 = (V >> 16) & 255u, b3 = V >> 24;
+                const u32 glo = (u32)(g & ((1ull << f) - 1ull));
+                // re-read the per-vector byte factors every iteration (held in
+                // registers they would need 256 VGPRs for 32 p-vectors): an
+                // opaque zero offset keeps the compiler from hoisting them
+                u32 zero;
+                asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+                const double(*a4v)[4] = (const double(*)[4])(&a4[0][0] + zero);
+#pragma unroll
+                for (int q = 0; q < kBatchMaxP; ++q) {
+                    if ((u32)q < P) {
+                        double F = a4v[q][0] * tb[q][b0];
+                        F = __builtin_fma(a4v[q][1], tb[q][b1], F);
+                        F = __builtin_fma(a4v[q][2], tb[q][b2], F);
+                        F = __builtin_fma(a4v[q][3], tb[q][b3], F);
+                        tot[q] = __builtin_fma(qlo[q][glo], F, tot[q]);
+                    }
+                }
+            }
+        }
+        // Q_hi of this segment and Q_L of the lane, then across the wavefront
+#pragma unroll
+        for (int q = 0; q < kBatchMaxP; ++q) {
+            if ((u32)q < P) {
+                const double *Tq = T + (u64)q * bat::kTablesFwd;
+                double qhi = 1.0;
+                for (u32 b = f; b < E.ubits; ++b) qhi *= Tq[bat::kQG + 2 * b + (u32)((g0 >> b) & 1ull)];
+                double h = tot[q] * qhi * Tq[bat::kQL + lane], l = 0.0;
+                bat::wave_sum_dd(h, l);
+                if (lane == 0) {
+                    wsum[w][q][0] = h;
+                    wsum[w][q][1] = l;
+                }
+            }
+        }
+        u64 c = bat::wave_sum_u64(cnt);
+        if (lane == 0) wcnt[w] = c;
+        __syncthreads();
+        if (tid < P) {
+            double h = 0.0, l = 0.0;
+            for (int v = 0; v < kBatchWaves; ++v) bat::dd_add(h, l, wsum[v][tid][0], wsum[v][tid][1]);
+            B.part[(item * kBatchMaxP + tid) * 2] = h;
+            B.part[(item * kBatchMaxP + tid) * 2 + 1] = l;
+        }
+        if (tid == 0) {
+            u64 cs = 0;
+            for (int v = 0; v < kBatchWaves; ++v) cs += wcnt[v];
+            B.pcount[item] = cs;
+        }
+        __syncthreads();
+    }
+}
+
+template __global__ void k_batched_dyn<16>(batk::BatchParams);
+template __global__ void k_batched_dyn<32>(batk::BatchParams);
+template __global__ void k_batched_dyn<64>(batk::BatchParams);
+
+// Entry e: thread q adds the entry's item partials of p-vector q in item
+// order; thread 0 of the entry holding p-vector 0 also adds the counts.
+extern "C" __global__ void __launch_bounds__(64)
+k_batched_reduce(const batk::BatchEntry *__restrict__ entries, const double *__restrict__ part,
+                 const u64 *__restrict__ pcount, u32 n_pvec, double *__restrict__ R, u64 *__restrict__ counts)
+{
+    const batk::BatchEntry E = entries[blockIdx.x];
+    const u32 q = threadIdx.x;
+    if (q < E.P) {
+        double h = 0.0, l = 0.0;
+        for (u64 it = E.item_begin; it < E.item_begin + E.n_items; ++it)
+            bat::dd_add(h, l, part[(it * batk::kBatchMaxP + q) * 2], part[(it * batk::kBatchMaxP + q) * 2 + 1]);
+        R[(u64)E.graph * n_pvec + E.pv_base + q] = h + l;
+    }
+    if (q == 0 && E.pv_base == 0) {
+        u64 c = 0;
+        for (u64 it = E.item_begin; it < E.item_begin + E.n_items; ++it) c += pcount[it];
+        counts[E.graph] = c;
+    }
+}
+
 // ------------------------------------------------------------ launchers
 namespace batk {
 
@@ -210,6 +383,30 @@ hipError_t finalize(hipStream_t st, const double *res, const u64 *count, const i
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, res, count, status, m, grad ? 1u : 0u, R, cnt, dRdp,
                        T1, T0, status_out);
+    return hipGetLastError();
+}
+
+hipError_t batched_tables(hipStream_t st, const BatchEntry *entries, const u32 *pair_entry, const u32 *pair_pv,
+                          const u64 *entry_p_off, const double *p, unsigned n_pairs, double *tables)
+{
+    hipLaunchKernelGGL(k_batched_tables, dim3(n_pairs), dim3(256), 0, st, entries, pair_entry, pair_pv, entry_p_off,
+                       p, tables);
+    return hipGetLastError();
+}
+
+hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, const BatchParams &B)
+{
+    const dim3 g(blocks), b(kBatchThreads);
+    if (nmax <= 16) hipLaunchKernelGGL(k_batched_dyn<16>, g, b, 0, st, B);
+    else if (nmax <= 32) hipLaunchKernelGGL(k_batched_dyn<32>, g, b, 0, st, B);
+    else hipLaunchKernelGGL(k_batched_dyn<64>, g, b, 0, st, B);
+    return hipGetLastError();
+}
+
+hipError_t batched_reduce(hipStream_t st, const BatchEntry *entries, unsigned n_entries, const double *part,
+                          const u64 *pcount, u32 n_pvec, double *R, u64 *counts)
+{
+    hipLaunchKernelGGL(k_batched_reduce, dim3(n_entries), dim3(64), 0, st, entries, part, pcount, n_pvec, R, counts);
     return hipGetLastError();
 }
 

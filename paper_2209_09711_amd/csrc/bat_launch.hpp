@@ -7,6 +7,42 @@
 
 namespace batk {
 
+// ---- batched form: many graphs x many probability vectors in one launch.
+constexpr int kBatchWaves = 8;                  // wavefronts per block (one block per CU: LDS-bound)
+constexpr int kBatchThreads = kBatchWaves * bat::kWave;
+constexpr int kBatchMaxP = 32;                  // probability vectors per entry
+constexpr int kBatchSegLog = 6;                 // iterations per wavefront work unit: 2^f
+
+// One (graph, group of <= 32 probability vectors).  Its work is split into
+// items of kBatchWaves * 2^f iterations; items of all entries form one queue.
+struct BatchEntry {
+    bat::u32 m, ubits, f, P;
+    bat::u32 n_nodes, s, t, n_relax;
+    bat::u32 relax_off;   // into the concatenated relaxation lists
+    bat::u32 graph, pv_base, pad;
+    bat::u64 item_begin, n_items;
+    bat::u64 tab_off;     // doubles: P consecutive forward table blocks
+};
+
+struct BatchParams {
+    const BatchEntry *entries;
+    const bat::u64 *item_start;   // [n_entries + 1], ascending
+    bat::u32 n_entries, check_every;
+    bat::u64 n_items;
+    const bat::u32 *codes, *rw;
+    const double *tables;
+    double *part;                 // [n_items][kBatchMaxP][2]
+    bat::u64 *pcount;             // [n_items]
+    unsigned long long *ctr;      // work queue head (zeroed before launch)
+};
+
+hipError_t batched_tables(hipStream_t st, const BatchEntry *entries, const bat::u32 *pair_entry,
+                          const bat::u32 *pair_pv, const bat::u64 *entry_p_off, const double *p, unsigned n_pairs,
+                          double *tables);
+hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, const BatchParams &B);
+hipError_t batched_reduce(hipStream_t st, const BatchEntry *entries, unsigned n_entries, const double *part,
+                          const bat::u64 *pcount, bat::u32 n_pvec, double *R, bat::u64 *counts);
+
 hipError_t build_tables(hipStream_t st, const double *p, bat::u32 m, bat::u32 f, double *T, int *status);
 hipError_t sweep_dyn(hipStream_t st, unsigned blocks, bool grad, int nmax, const bat::KParams &K);
 hipError_t reduce(hipStream_t st, const double *part, const bat::u64 *pcount, bat::u64 n_chunks, bat::u32 ncol,

@@ -157,7 +157,7 @@ def test_edge_cases(jit):
         assert cnt == 12 and abs(R - (1 - 0.4 * 0.3)) <= 1e-15
         # m = 11 and 12: exactly one word/wave, and one iteration bit
         for m in (5, 10, 11, 12):
-            net = W.random_connected(8, m, seed=m, p_lo=0.1, p_hi=0.9)
+            net = W.random_connected(6, m, seed=m, p_lo=0.1, p_hi=0.9)
             R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
             o = oracle.net_reliability(net)
             assert cnt == o.count and rel_ok(R, o.sum)
@@ -366,3 +366,59 @@ def test_async_invalid_probability():
                             st.data_ptr(), torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     assert int(st.item()) == B.BAT_EINVAL and np.isnan(R.item())
+
+
+# ------------------------------------------------------------------ batched
+
+def _batch_inputs(seed, n_graphs, n_pvec):
+    rng = np.random.default_rng(seed)
+    graphs, pblocks = [], []
+    for g in range(n_graphs):
+        if g % 5 == 4:
+            net = W.random_multigraph(int(rng.integers(2, 7)), int(rng.integers(0, 12)), seed=int(rng.integers(1 << 30)))
+        else:
+            n = int(rng.integers(3, 15))
+            m = int(rng.integers(n - 1, min(24, n * (n - 1) // 2) + 1))
+            net = W.random_connected(n, m, seed=int(rng.integers(1 << 30)))
+            s, t = (int(x) for x in rng.choice(n, 2, replace=False))
+            net.s, net.t = s, t
+        graphs.append((net.n, net.arcs, net.s, net.t))
+        pb = rng.uniform(0.0, 1.0, size=(n_pvec, len(net.arcs)))
+        if pb.size:
+            pb[rng.random(pb.shape) < 0.05] = 1.0
+        pblocks.append(pb)
+    return graphs, pblocks
+
+
+@pytest.mark.parametrize("n_pvec", [1, 7, 32, 45])
+def test_batched_vs_plain_and_oracle(n_pvec):
+    B = _B()
+    graphs, pblocks = _batch_inputs(500 + n_pvec, 14, n_pvec)
+    say("batched", len(graphs), n_pvec)
+    R, cnt = B.bat_reliability_batched(graphs, pblocks)
+    for g, (n, arcs, s, t) in enumerate(graphs):
+        for j in sorted({0, n_pvec // 2, n_pvec - 1}):
+            Rp, cp = B.bat_reliability(n, arcs, pblocks[g][j], s, t)
+            assert cnt[g] == cp and rel_ok(R[g, j], Rp), (g, j, R[g, j], Rp)
+        if len(arcs) <= 16:
+            o = oracle.reliability(n, arcs, pblocks[g][0], s, t)
+            assert cnt[g] == o.count and rel_ok(R[g, 0], o.sum)
+
+
+def test_batched_config3_workload():
+    """256 graphs x 32 probability vectors in one persistent launch."""
+    B = _B()
+    nets, pvs = W.config3()
+    graphs = [(n.n, n.arcs, n.s, n.t) for n in nets]
+    say("config3 batched", len(graphs))
+    R, cnt = B.bat_reliability_batched(graphs, pvs)
+    R2, cnt2 = B.bat_reliability_batched(graphs, pvs)
+    assert np.array_equal(R, R2) and np.array_equal(cnt, cnt2)       # deterministic
+    for g, net in enumerate(nets):
+        Rd, cd = frontier_dp.reliability(net.n, net.arcs, pvs[g][0], net.s, net.t)
+        assert cnt[g] == cd and rel_ok(R[g, 0], Rd), (g, R[g, 0], Rd)
+    for g in range(0, len(nets), 17):
+        net = nets[g]
+        for j in (5, 31):
+            Rp, cp = B.bat_reliability(net.n, net.arcs, pvs[g][j], net.s, net.t)
+            assert cp == cnt[g] and rel_ok(R[g, j], Rp)
