@@ -46,6 +46,16 @@ class bat_launch_info(ctypes.Structure):
 
 
 def _load():
+    # PyTorch wheels bundle their own HIP runtime under the same soname
+    # (libamdhip64.so.7) but link it by its unversioned name.  If torch is
+    # loaded first, this library's libamdhip64.so.7 dependency binds to that
+    # same runtime, so torch tensors and streams are valid here.  If this
+    # library came first, torch would load a second runtime and fail to see
+    # the GPU.  So load torch first whenever it is installed.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
                           f"g.build()'` (the HIP library is required; there is no CPU fallback)")

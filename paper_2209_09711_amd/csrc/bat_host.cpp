@@ -64,7 +64,7 @@ int fail(int code, const char *fmt, ...)
 
 // ------------------------------------------------------------ options
 struct Options {
-    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1};
+    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{2}, autotune{1};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
