@@ -44,7 +44,21 @@ def parse():
     ap.add_argument("--cpu-sample-log2", type=int, default=30,
                     help="log2 of the state vectors in the oracle's timed sample")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--copy-ref-gib", type=float, default=0.0,
+                    help="only run a plain device-to-device copy of this many GiB (the reference kernel "
+                         "that scales the HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_reference(gib: float):
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_reference_bytes_read": 4 * n, "copy_reference_bytes_written": 4 * n}), flush=True)
 
 
 def cpu_baseline(net, sample_log2: int):
@@ -72,6 +86,9 @@ def cpu_baseline(net, sample_log2: int):
 
 def main():
     a = parse()
+    if a.copy_ref_gib > 0:
+        copy_reference(a.copy_ref_gib)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the enumeration would shard "
               f"by counter ranges across GPUs, which this build does not launch.", file=sys.stderr)
