@@ -64,7 +64,7 @@ int fail(int code, const char *fmt, ...)
 
 // ------------------------------------------------------------ options
 struct Options {
-    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{2}, autotune{1};
+    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -160,7 +160,7 @@ struct Bcc {
 struct Plan {
     int n = 0, m = 0, s = 0, t = 0;
     int N = 0, S = 0, T = 0;              // relevant nodes, renumbered
-    std::vector<int> ru, rv, rb;          // relaxations (forward order): nodes and counter bit
+    std::vector<int> ru, rv, rb, rd;      // relaxations (forward order): nodes, counter bit, discovers rv
     std::vector<u32> code, wconst;        // the same for the generic kernel
     std::string structure;                // JIT key (graph structure only)
 };
@@ -193,7 +193,7 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
     std::vector<char> listed(m, 0);
     id[s] = 0;
     order.push_back(s);
-    P.ru.clear(); P.rv.clear(); P.rb.clear();
+    P.ru.clear(); P.rv.clear(); P.rb.clear(); P.rd.clear();
     for (size_t h = 0; h < order.size(); ++h) {
         int u = order[h];
         for (int i = 0; i < m; ++i) {
@@ -201,11 +201,14 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
             int a = arcs[i].u, b = arcs[i].v;
             if (a != u && b != u) continue;
             int w = (a == u) ? b : a;
+            int discovers = 0;
             if (id[w] < 0) {
                 id[w] = (int)order.size();
                 order.push_back(w);
+                discovers = 1;
             }
             listed[i] = 1;
+            P.rd.push_back(discovers);
             P.ru.push_back(id[u]);
             P.rv.push_back(id[w]);
             P.rb.push_back(m - 1 - i);
@@ -227,7 +230,8 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
     std::string sdesc = "N" + std::to_string(P.N) + " S" + std::to_string(P.S) + " T" + std::to_string(P.T) +
                         " m" + std::to_string(m) + " :";
     for (size_t k = 0; k < P.ru.size(); ++k)
-        sdesc += " " + std::to_string(P.ru[k]) + "," + std::to_string(P.rv[k]) + "," + std::to_string(P.rb[k]);
+        sdesc += " " + std::to_string(P.ru[k]) + "," + std::to_string(P.rv[k]) + "," + std::to_string(P.rb[k]) +
+                 (P.rd[k] ? "d" : "");
     P.structure = sdesc;
 }
 
@@ -319,6 +323,7 @@ std::string jit_source(const Plan &P, bool grad)
     arr("RU", P.ru);
     arr("RV", P.rv);
     arr("RB", P.rb);
+    arr("RD", P.rd);
     s += "};\n";
     if (grad)
         s += "extern \"C\" __global__ void __launch_bounds__(256) bat_grad_jit(bat::KParams P) {\n"
