@@ -324,6 +324,12 @@ std::string jit_source(const Plan &P, bool grad)
     arr("RV", P.rv);
     arr("RB", P.rb);
     arr("RD", P.rd);
+    // relaxations of counter bits 11, 12, 13 (the chained iteration arcs)
+    int ck[3] = {-1, -1, -1};
+    for (size_t k = 0; k < nr; ++k)
+        if (P.rb[k] >= bat::kWordBits && P.rb[k] < bat::kWordBits + 3) ck[P.rb[k] - bat::kWordBits] = (int)k;
+    s += "  static constexpr int CK[3] = {" + std::to_string(ck[0]) + "," + std::to_string(ck[1]) + "," +
+         std::to_string(ck[2]) + "};\n";
     s += "};\n";
     if (grad)
         s += "extern \"C\" __global__ void __launch_bounds__(256) bat_grad_jit(bat::KParams P) {\n"
@@ -412,7 +418,6 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
     const u32 ubits = m > (u32)bat::kWordBits ? m - bat::kWordBits : 0u;
     const u64 g_first = rq.c_lo >> bat::kWordBits;
     const u64 g_last = (rq.c_hi - 1) >> bat::kWordBits;
-    const u64 iters = g_last - g_first + 1;
 
     Options &O = opts();
     TuneChoice tc{(int)O.chunk_log2.load(), (int)O.check_every.load(), (int)O.jit.load()};
@@ -425,6 +430,16 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
     if (rq.force_check >= 0) tc.check_every = rq.force_check;
     if (rq.force_jit >= 0) tc.jit = rq.force_jit;
 
+    // pick the kernel
+    bool use_jit = false;
+    if (tc.jit == 1) use_jit = true;
+    else if (tc.jit == 2) use_jit = (rq.c_hi - rq.c_lo) >= (1ull << 32) || (P.N > 32 && (rq.c_hi - rq.c_lo) >= (1ull << 22));
+    // warm-started chains need the specialised closure and >= 3 iteration bits
+    const bool chain = use_jit && ubits >= 3 && !P.ru.empty();
+    const u64 g_base = chain ? (g_first & ~7ull) : g_first;
+    const u64 g_end = chain ? (g_last | 7ull) : g_last;
+    const u64 iters = g_end - g_base + 1;
+
     int clog = tc.chunk_log2;
     if (clog <= 0) {  // aim at ~64 work items per CU, at most 4096 iterations each
         u64 target = iters / ((u64)std::max(D.cus, 1) * 64ull);
@@ -432,7 +447,9 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
         while (clog < 12 && (2ull << clog) <= target) ++clog;
     }
     clog = std::min(clog, 20);
+    if (chain) clog = std::max(clog, 3);
     u32 f = (u32)std::max<int64_t>(0, std::min<int64_t>(O.seg_log2.load(), bat::kMaxSegLog));
+    if (chain) f = std::max<u32>(f, 3);
     if (f > ubits) f = ubits;
 
     bat::KParams K;
@@ -441,12 +458,15 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
     K.c_hi = rq.c_hi;
     K.g_first = g_first;
     K.g_last = g_last;
+    K.g_base = g_base;
+    K.g_end = g_end;
     K.chunk_iters = 1ull << clog;
     K.n_chunks = (iters + K.chunk_iters - 1) >> clog;
     K.m = m;
     K.ubits = ubits;
     K.seg_log = f;
     K.check_every = tc.check_every >= 2 ? 2u : 1u;
+    K.chain = chain ? 1u : 0u;
     K.ncol = rq.grad ? 1u + 2u * m : 1u;
     K.n_nodes = (u32)P.N;
     K.s = (u32)P.S;
@@ -489,10 +509,6 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
         HIPCHK(hipMemcpyAsync((void *)K.rw, P.wconst.data(), sizeof(u32) * P.code.size(), hipMemcpyHostToDevice, stream));
     }
 
-    // pick the kernel
-    bool use_jit = false;
-    if (tc.jit == 1) use_jit = true;
-    else if (tc.jit == 2) use_jit = (rq.c_hi - rq.c_lo) >= (1ull << 32) || (P.N > 32 && (rq.c_hi - rq.c_lo) >= (1ull << 22));
     hipFunction_t jfn = nullptr;
     double jit_ms = 0.0;
     if (use_jit) {

@@ -312,9 +312,15 @@ def test_grad_birnbaum_bruteforce():
 
 # --------------------------------------------------------------- range API
 
-def test_ranges_compose():
+@pytest.mark.parametrize("jit", KERNELS)
+def test_ranges_compose(jit):
     B = _B()
     net = W.random_connected(14, 27, seed=31, p_lo=0.4, p_hi=0.99)
+    with options(BAT_JIT=jit):
+        _ranges_compose(B, net)
+
+
+def _ranges_compose(B, net):
     full = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
     cuts = [0, 1, 2047, 2048, 70001, 1 << 20, (1 << 27) - 5, 1 << 27]
     hi = lo = 0.0
@@ -332,6 +338,26 @@ def test_ranges_compose():
         T0 += r.T0
     assert cnt == full.count and rel_ok(hi + lo, full.R)
     assert np.allclose(T1, full.T1, rtol=1e-12, atol=0) and np.allclose(T0, full.T0, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_ragged_ranges_specialised_vs_oracle(seed):
+    """Ranges that start and end inside an 8-iteration chain block (the
+    specialised kernel sweeps whole blocks and masks what lies outside)."""
+    B = _B()
+    rng = np.random.default_rng(seed)
+    net = W.random_connected(13, 24 + seed, seed=70 + seed, p_lo=0.3, p_hi=0.99)
+    total = 1 << net.m
+    with options(BAT_JIT=1):
+        for _ in range(4):
+            lo = int(rng.integers(0, total - (1 << 18)))
+            hi = lo + int(rng.integers(1, 1 << 18))
+            say("ragged", net.name, lo, hi)
+            r = B.bat_reliability_range(net.n, net.arcs, net.p, net.s, net.t, lo, hi, grad=True)
+            o = oracle.reliability_range(net.n, net.arcs, net.p, net.s, net.t, lo, hi, grad=True)
+            assert r.count == o.count and rel_ok(r.R, o.sum)
+            assert np.allclose(r.T1, o.T1, rtol=1e-12, atol=1e-300)
+            assert np.allclose(r.T0, o.T0, rtol=1e-12, atol=1e-300)
 
 
 # ------------------------------------------------------------------- torch
