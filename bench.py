@@ -33,6 +33,21 @@ CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_LANE_OPS = CUS * LANES * CLOCK_HZ            # 3.93e13 int32 lane-ops/s
 PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 1.26e15 bit-ops/s
 
+# HBM bytes per launch of the enumeration kernel on this workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain 1 GiB copy
+# (profiles/bat_fwd_jit_grid5x5_m40.md), keyed by the hash of the kernel and
+# host sources they were measured on; any other source reports null.
+MEASURED_TRAFFIC = {"4f3d07213b5b": (108.1 * 2.0 + 3072.0 * 1.0) * 1024}
+
+
+def source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("bat_device.hpp", "bat_host.cpp"):
+        with open(os.path.join(ROOT, "paper_2209_09711_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -184,6 +199,32 @@ def main():
         out["fwd_grad_vs_fwd"] = {"workload": "random n=18 m=36 (seed 220909711/4), R + 36 gradients",
                                   "fwd_kernel_ms": min(fw), "fwd_grad_kernel_ms": min(gr),
                                   "ratio": min(gr) / min(fw)}
+        # batched: one persistent launch vs the plain forward on every
+        # (graph, probability vector) pair of the same workload
+        nets, pvs = W.config3()
+        graphs = [(g.n, g.arc_array(), g.s, g.t) for g in nets]
+        B.bat_reliability_batched(graphs, pvs)
+        t0 = time.perf_counter()
+        Rb, cb = B.bat_reliability_batched(graphs, pvs)
+        bw = time.perf_counter() - t0
+        bk = B.bat_last_launch().kernel_ms
+        t0 = time.perf_counter()
+        pk = 0.0
+        worst = 0.0
+        for gi, (n_, a_, s_, t_) in enumerate(graphs):
+            for j in range(pvs[gi].shape[0]):
+                Rp, cp = B.bat_reliability(n_, a_, pvs[gi][j], s_, t_)
+                pk += B.bat_last_launch().kernel_ms
+                assert cp == cb[gi]
+                worst = max(worst, abs(Rp - Rb[gi, j]) / Rp if Rp else abs(Rb[gi, j]))
+        pw = time.perf_counter() - t0
+        vec = sum(1 << g.m for g in nets)
+        out["batched_vs_plain"] = {
+            "workload": f"{len(nets)} random graphs, n 8-16, m 16-28 (seed 220909711/3), "
+                        f"{pvs[0].shape[0]} p-vectors each, {vec} state vectors x {pvs[0].shape[0]}",
+            "batched_wall_ms": bw * 1e3, "batched_kernel_ms": bk,
+            "plain_wall_ms": pw * 1e3, "plain_kernel_ms_sum": pk,
+            "speedup_wall": pw / bw, "max_rel_diff": worst}
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -200,7 +241,8 @@ def main():
     if insp is not None:
         achieved = nvec * insp / kern_s
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_BIT_OPS / 1e12,
-                           "unit": "Tbitop/s", "frac": achieved / PEAK_BIT_OPS, "traffic": None,
+                           "unit": "Tbitop/s", "frac": achieved / PEAK_BIT_OPS,
+                           "traffic": MEASURED_TRAFFIC.get(source_hash()),
                            "work_per_vector": insp, "work_unit": "PLSA arc inspections (1 bit-op each)"}
     line = json.dumps(out)
     print(line, flush=True)

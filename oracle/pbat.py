@@ -123,8 +123,18 @@ def run(n, arcs, p, s, t, chi: int, divisions: Optional[Sequence[int]] = None,
 
 
 def spread_divisions(chi: int, k: int) -> List[int]:
-    """k divisions spread evenly over 1..chi (for sampled timing and checks:
-    the cost of a vector varies along the counter, so a prefix slice is not
-    representative)."""
+    """k distinct divisions spread over 1..chi (for sampled timing and
+    checks: the cost of a vector varies along the counter, so a prefix slice
+    is not representative).  Golden-ratio (Weyl) sequence: evenly spread,
+    and unlike evenly strided indices it varies every bit of the division
+    prefix, i.e. every one of the leading arcs' states."""
     k = max(1, min(k, chi))
-    return sorted({1 + (j * chi) // k for j in range(k)})
+    phi = 0.6180339887498949
+    out, seen, j = [], set(), 0
+    while len(out) < k:
+        i = 1 + int(((j + 1) * phi % 1.0) * chi)
+        j += 1
+        if i not in seen:
+            seen.add(i)
+            out.append(i)
+    return sorted(out)

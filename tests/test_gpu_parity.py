@@ -360,6 +360,19 @@ def test_ragged_ranges_specialised_vs_oracle(seed):
             assert np.allclose(r.T0, o.T0, rtol=1e-12, atol=1e-300)
 
 
+def test_autotune_choice_keeps_results():
+    B = _B()
+    net = W.random_connected(16, 34, seed=8, p_lo=0.6, p_hi=0.99)
+    R0, c0 = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+    ns = B.bat_autotune(net.n, net.arcs, net.p, net.s, net.t)
+    say("autotune ns/vector", ns)
+    assert 0.0 < ns < 1.0
+    R1, c1 = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+    assert c1 == c0 and rel_ok(R1, R0)
+    g = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+    assert g.count == c0 and rel_ok(g.R, R0)
+
+
 # ------------------------------------------------------------------- torch
 
 def test_torch_autograd_and_async():
