@@ -128,6 +128,12 @@ def main():
     cold_s = time.perf_counter() - t0
     info = B.bat_last_launch()
     jit_ms = info.jit_ms
+    # autotune (one-time, reported separately): work-item size, convergence
+    # test cadence, kernel kind and arc-to-bit order, timed on spread slices
+    t0 = time.perf_counter()
+    tune_ns = B.bat_autotune(net.n, arcs, net.p, net.s, net.t)
+    tune_s = time.perf_counter() - t0
+    R_cold, cnt_cold = B.bat_reliability(net.n, arcs, net.p, net.s, net.t)
 
     p_dev = torch.tensor(net.p, dtype=torch.float64, device=dev)
     R_dev = torch.zeros((), dtype=torch.float64, device=dev)
@@ -180,7 +186,8 @@ def main():
         "R": R,
         "R_hex": R.hex(),
         "feasible_count": count,
-        "time_to_exact_R_s": {"cold_incl_jit": cold_s, "warm": warm_s, "jit_compile_ms": jit_ms},
+        "time_to_exact_R_s": {"cold_incl_jit": cold_s, "warm": warm_s, "jit_compile_ms": jit_ms,
+                              "autotune_s": tune_s, "autotune_ns_per_vector": tune_ns},
         "kernel_ms_mean": float(np.mean(kern_ms)),
         "specialised_kernel": bool(li.specialised),
         "relaxations_per_sweep": li.relaxations,
@@ -188,6 +195,7 @@ def main():
 
     if not a.no_extras:
         c4 = W.config4()
+        B.bat_autotune(c4.n, c4.arcs, c4.p, c4.s, c4.t)
         B.bat_reliability(c4.n, c4.arcs, c4.p, c4.s, c4.t)          # warm both kernels
         B.bat_reliability_grad(c4.n, c4.arcs, c4.p, c4.s, c4.t)
         fw, gr = [], []

@@ -154,6 +154,13 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
  *   "BAT_CHECK_EVERY"  1 = convergence test after every sweep, 2 = after
  *                      every forward+backward pair
  *   "BAT_AUTOTUNE"     1 = let bat_autotune's cached choices apply
+ *   "BAT_PERM"         which arcs take the low counter bits in whole-range
+ *                      sweeps: -1 = the tuned choice, else kind 3; 0 = the
+ *                      paper's order, 1..3 = orders that put arcs near t on
+ *                      the in-wavefront bits and pruned or mid-graph arcs on
+ *                      the chained iteration bits (R and counts never
+ *                      depend on it; the range entry point always uses the
+ *                      paper's order)
  * Unknown keys return BAT_EINVAL.
  */
 int bat_set_option(const char *key, int64_t value);

@@ -64,7 +64,7 @@ int fail(int code, const char *fmt, ...)
 
 // ------------------------------------------------------------ options
 struct Options {
-    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1};
+    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -76,6 +76,7 @@ struct Options {
         rd("BAT_SEG_LOG2", seg_log2);
         rd("BAT_CHECK_EVERY", check_every);
         rd("BAT_AUTOTUNE", autotune);
+        rd("BAT_PERM", perm);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -85,6 +86,7 @@ struct Options {
         if (!strcmp(k, "BAT_SEG_LOG2")) return &seg_log2;
         if (!strcmp(k, "BAT_CHECK_EVERY")) return &check_every;
         if (!strcmp(k, "BAT_AUTOTUNE")) return &autotune;
+        if (!strcmp(k, "BAT_PERM")) return &perm;
         return nullptr;
     }
 };
@@ -159,18 +161,76 @@ struct Bcc {
 
 struct Plan {
     int n = 0, m = 0, s = 0, t = 0;
+    int perm = 0;                         // arc -> counter bit assignment kind (0 = the paper's order)
+    std::vector<int> cb_of_arc;           // counter bit of each arc
+    std::vector<unsigned char> row;       // row[j] = arc at counter bit m-1-j
     int N = 0, S = 0, T = 0;              // relevant nodes, renumbered
     std::vector<int> ru, rv, rb, rd;      // relaxations (forward order): nodes, counter bit, discovers rv
     std::vector<u32> code, wconst;        // the same for the generic kernel
     std::string structure;                // JIT key (graph structure only)
 };
 
-void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, Plan &P)
+// Which arc sits at which counter bit.  Kind 0 is the paper's backward
+// order (arc i at bit m-1-i), the only one the range entry point uses, since
+// its indices are the paper's.  The others only reorder a full sweep (R and
+// the count are sums over all vectors):
+//   1: the 11 in-wavefront bits (word + lane) on the relevant arcs latest in
+//      BFS order (nearest t), the 3 chained iteration bits on pruned arcs
+//      first (their warm steps are free), then on the next-latest arcs;
+//   2: in-wavefront bits as in kind 0, chained bits on pruned arcs, then on
+//      arcs from the middle of the BFS order;
+//   3: in-wavefront bits as in kind 1, chained bits as in kind 2.
+// Every other arc keeps the relative order of kind 0.
+constexpr int kPermKinds = 4;
+constexpr int kDefaultPerm = 3;  // untuned whole sweeps
+
+void assign_bits(int m, const std::vector<int> &rel_bfs, const std::vector<char> &rel, int kind,
+                 std::vector<int> &cb_of_arc)
+{
+    cb_of_arc.assign(m, -1);
+    if (kind == 0 || m <= bat::kWordBits) {
+        for (int i = 0; i < m; ++i) cb_of_arc[i] = m - 1 - i;
+        return;
+    }
+    std::vector<int> by_cb;
+    std::vector<char> used(m, 0);
+    auto take = [&](int a) {
+        if (a >= 0 && a < m && !used[a]) {
+            used[a] = 1;
+            by_cb.push_back(a);
+        }
+    };
+    const int nr = (int)rel_bfs.size();
+    // in-wavefront bits
+    if (kind == 2) {
+        for (int c = 0; c < bat::kWordBits; ++c) take(m - 1 - c);
+    } else {
+        for (int k = nr - 1; k >= 0 && (int)by_cb.size() < bat::kWordBits; --k) take(rel_bfs[k]);
+        for (int i = m - 1; i >= 0 && (int)by_cb.size() < bat::kWordBits; --i) take(i);
+    }
+    // chained iteration bits
+    const size_t want = bat::kWordBits + 3;
+    for (int i = m - 1; i >= 0 && by_cb.size() < want; --i)
+        if (!rel[i]) take(i);
+    if (kind == 1) {
+        for (int k = nr - 1; k >= 0 && by_cb.size() < want; --k) take(rel_bfs[k]);
+    } else {
+        for (int d = 0; d < nr && by_cb.size() < want; ++d) {
+            int k = nr / 2 + ((d & 1) ? -(d + 1) / 2 : d / 2);
+            if (k >= 0 && k < nr) take(rel_bfs[k]);
+        }
+    }
+    for (int i = m - 1; i >= 0; --i) take(i);
+    for (int c = 0; c < m; ++c) cb_of_arc[by_cb[c]] = c;
+}
+
+void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, Plan &P, int perm_kind = 0)
 {
     P.n = n;
     P.m = m;
     P.s = s;
     P.t = t;
+    P.perm = perm_kind;
     Bcc B;
     B.n = n;
     B.m = m;
@@ -189,11 +249,11 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
     B.dfs(s, -1);
 
     // BFS from s over relevant arcs: node numbering and sweep order
-    std::vector<int> id(n, -1), order;
+    std::vector<int> id(n, -1), order, rel_bfs, disc_flag;
     std::vector<char> listed(m, 0);
+    std::vector<std::pair<int, int>> ends;
     id[s] = 0;
     order.push_back(s);
-    P.ru.clear(); P.rv.clear(); P.rb.clear(); P.rd.clear();
     for (size_t h = 0; h < order.size(); ++h) {
         int u = order[h];
         for (int i = 0; i < m; ++i) {
@@ -208,15 +268,39 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
                 discovers = 1;
             }
             listed[i] = 1;
-            P.rd.push_back(discovers);
-            P.ru.push_back(id[u]);
-            P.rv.push_back(id[w]);
-            P.rb.push_back(m - 1 - i);
+            rel_bfs.push_back(i);
+            ends.push_back({id[u], id[w]});
+            disc_flag.push_back(discovers);
         }
     }
     if (id[t] < 0) {  // s and t never connected: keep both as nodes, no arcs
         id[t] = (int)order.size();
         order.push_back(t);
+    }
+    std::vector<char> rel(m, 0);
+    for (int i = 0; i < m; ++i) rel[i] = B.rel[i];
+    assign_bits(m, rel_bfs, rel, perm_kind, P.cb_of_arc);
+    {  // must be a bijection onto [0, m); otherwise use the paper's order
+        std::vector<char> hit(std::max(m, 1), 0);
+        bool ok = true;
+        for (int i = 0; i < m; ++i) {
+            int c = P.cb_of_arc[i];
+            if (c < 0 || c >= m || hit[c]) ok = false;
+            else hit[c] = 1;
+        }
+        if (!ok) {
+            P.perm = 0;
+            for (int i = 0; i < m; ++i) P.cb_of_arc[i] = m - 1 - i;
+        }
+    }
+    P.row.assign(std::max(m, 1), 0);
+    for (int i = 0; i < m; ++i) P.row[m - 1 - P.cb_of_arc[i]] = (unsigned char)i;
+    P.ru.clear(); P.rv.clear(); P.rb.clear(); P.rd.clear();
+    for (size_t k = 0; k < rel_bfs.size(); ++k) {
+        P.ru.push_back(ends[k].first);
+        P.rv.push_back(ends[k].second);
+        P.rb.push_back(P.cb_of_arc[rel_bfs[k]]);
+        P.rd.push_back(disc_flag[k]);
     }
     P.N = (int)order.size();
     P.S = 0;
@@ -384,10 +468,19 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, do
 
 // ------------------------------------------------------------ autotune cache
 struct TuneChoice {
-    int chunk_log2, check_every, jit;
+    int chunk_log2, check_every, jit, perm;
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneChoice> g_tune;
+
+// The graph itself (node count, arcs, terminals): what tuned choices are
+// remembered under.
+std::string graph_key(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t)
+{
+    std::string k = std::to_string(n) + "/" + std::to_string(s) + "/" + std::to_string(t) + ":";
+    for (int32_t i = 0; i < m; ++i) k += std::to_string(arcs[i].u) + "-" + std::to_string(arcs[i].v) + ",";
+    return k;
+}
 
 // ------------------------------------------------------------ the sweep
 struct Request {
@@ -396,15 +489,40 @@ struct Request {
     const double *p_dev;    // device probabilities
     u64 c_lo, c_hi;
     bool grad;
-    // forced knobs (autotuner); -1 = from options
-    int force_chunk_log2 = -1, force_check = -1, force_jit = -1;
+    // forced knobs (autotuner); -1 = from options / the tuned choice
+    int force_chunk_log2 = -1, force_check = -1, force_jit = -1, force_perm = -1;
+    // timing sample (autotuner): sweep only this many work items, spread
+    // over the whole counter by an odd multiplier (0 = everything)
+    u64 sample_items = 0;
 };
+
+// Options, then the tuned choice for this graph (if any and enabled), then
+// what the request forces.
+TuneChoice choose(const DeviceInfo &D, const std::string &gkey, bool grad, const Request *rq)
+{
+    Options &O = opts();
+    TuneChoice tc{(int)O.chunk_log2.load(), (int)O.check_every.load(), (int)O.jit.load(), -1};
+    if (O.autotune.load()) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(std::to_string(D.id) + (grad ? " grad " : " fwd ") + gkey);
+        if (it != g_tune.end()) tc = it->second;
+    }
+    if (O.perm.load() >= 0) tc.perm = (int)O.perm.load();
+    if (rq) {
+        if (rq->force_chunk_log2 >= 0) tc.chunk_log2 = rq->force_chunk_log2;
+        if (rq->force_check >= 0) tc.check_every = rq->force_check;
+        if (rq->force_jit >= 0) tc.jit = rq->force_jit;
+        if (rq->force_perm >= 0) tc.perm = rq->force_perm;
+    }
+    return tc;
+}
 
 struct Launch {
     void *ws = nullptr;     // workspace (stream-ordered)
     double *res = nullptr;  // [ncol][2]
     u64 *count = nullptr;
     int *status = nullptr;
+    const unsigned char *cb_of_arc = nullptr;
     u32 ncol = 1;
 };
 
@@ -412,24 +530,14 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Queue tables + sweep + reduce on `stream`.  Allocates the workspace with
 // hipMallocAsync; the caller frees it on the same stream.
-int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream_t stream, Launch &L)
+int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const TuneChoice &tc, hipStream_t stream,
+                Launch &L)
 {
     const u32 m = (u32)rq.m;
     const u32 ubits = m > (u32)bat::kWordBits ? m - bat::kWordBits : 0u;
     const u64 g_first = rq.c_lo >> bat::kWordBits;
     const u64 g_last = (rq.c_hi - 1) >> bat::kWordBits;
-
     Options &O = opts();
-    TuneChoice tc{(int)O.chunk_log2.load(), (int)O.check_every.load(), (int)O.jit.load()};
-    if (O.autotune.load()) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find(std::to_string(D.id) + (rq.grad ? " grad " : " fwd ") + P.structure);
-        if (it != g_tune.end()) tc = it->second;
-    }
-    if (rq.force_chunk_log2 >= 0) tc.chunk_log2 = rq.force_chunk_log2;
-    if (rq.force_check >= 0) tc.check_every = rq.force_check;
-    if (rq.force_jit >= 0) tc.jit = rq.force_jit;
-
     // pick the kernel
     bool use_jit = false;
     if (tc.jit == 1) use_jit = true;
@@ -449,6 +557,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
     clog = std::min(clog, 20);
     if (chain) clog = std::max(clog, 3);
     u32 f = (u32)std::max<int64_t>(0, std::min<int64_t>(O.seg_log2.load(), bat::kMaxSegLog));
+    if (rq.grad) f = std::min<u32>(f, bat::kGradFastMax);
     if (chain) f = std::max<u32>(f, 3);
     if (f > ubits) f = ubits;
 
@@ -462,6 +571,13 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
     K.g_end = g_end;
     K.chunk_iters = 1ull << clog;
     K.n_chunks = (iters + K.chunk_iters - 1) >> clog;
+    K.chunk_mul = 1;
+    K.chunk_mask = ~0ull;
+    if (rq.sample_items && rq.sample_items < K.n_chunks && (K.n_chunks & (K.n_chunks - 1)) == 0) {
+        K.chunk_mul = 0x9E3779B97F4A7C15ull;  // odd: a bijection modulo n_chunks
+        K.chunk_mask = K.n_chunks - 1;
+        K.n_chunks = rq.sample_items;
+    }
     K.m = m;
     K.ubits = ubits;
     K.seg_log = f;
@@ -480,6 +596,8 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
     off = align_up(off + sizeof(double) * bat::kTables, 256);
     const size_t o_st = off;
     off = align_up(off + 64, 256);
+    const size_t o_map = off;  // row[64] | cb_of_arc[64]
+    off = align_up(off + 128, 256);
     const size_t o_rl = off;
     off = align_up(off + sizeof(u32) * (P.code.size() + 1), 256);
     const size_t o_rw = off;
@@ -504,6 +622,16 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
     L.res = (double *)(ws + o_res);
     L.count = (u64 *)(ws + o_cnt);
     L.status = (int *)(ws + o_st);
+    unsigned char maps[128];
+    memset(maps, 0, sizeof maps);
+    for (int i = 0; i < P.m; ++i) {
+        maps[i] = P.row[i];
+        maps[64 + i] = (unsigned char)P.cb_of_arc[i];
+    }
+    HIPCHK(hipMemcpyAsync(ws + o_map, maps, sizeof maps, hipMemcpyHostToDevice, stream));
+    const bool identity = P.perm == 0 || P.m <= bat::kWordBits;
+    const unsigned char *d_row = identity ? nullptr : (const unsigned char *)(ws + o_map);
+    L.cb_of_arc = identity ? nullptr : (const unsigned char *)(ws + o_map + 64);
     if (!P.code.empty()) {
         HIPCHK(hipMemcpyAsync((void *)K.relax, P.code.data(), sizeof(u32) * P.code.size(), hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync((void *)K.rw, P.wconst.data(), sizeof(u32) * P.code.size(), hipMemcpyHostToDevice, stream));
@@ -519,7 +647,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
     int rc = events_ready();
     if (rc) return rc;
     HIPCHK(hipEventRecord(t_state.ev[0], stream));
-    HIPCHK(batk::build_tables(stream, rq.p_dev, m, f, (double *)K.tables, (int *)K.status));
+    HIPCHK(batk::build_tables(stream, rq.p_dev, d_row, m, f, (double *)K.tables, (int *)K.status));
     HIPCHK(hipEventRecord(t_state.ev[1], stream));
     const u64 blocks = (K.n_chunks + bat::kWavesPerBlock - 1) / bat::kWavesPerBlock;
     if (blocks > 0x7fffffffull) return fail(BAT_ETOOBIG, "too many work items (%llu)", (unsigned long long)blocks);
@@ -536,7 +664,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, hipStream
     bat_launch_info &I = t_state.info;
     memset(&I, 0, sizeof I);
     I.jit_ms = jit_ms;
-    I.vectors = rq.c_hi - rq.c_lo;
+    I.vectors = std::min<u64>(rq.c_hi - rq.c_lo, K.n_chunks * K.chunk_iters << bat::kWordBits);
     I.specialised = use_jit ? 1 : 0;
     I.chunk_log2 = clog;
     I.n_chunks = (int32_t)std::min<u64>(K.n_chunks, 0x7fffffff);
@@ -551,25 +679,37 @@ struct Prepared {
     hipStream_t stream = nullptr;
 };
 
-int prepare(int32_t n, int32_t m, const bat_arc *arcs, const double *p_host, int32_t s, int32_t t,
-            Prepared &X)
+// Validate, pick the launch choices and plan.  full_range: the whole
+// counter, where any arc order may be used; otherwise the paper's order.
+int prepare(int32_t n, int32_t m, const bat_arc *arcs, const double *p_host, int32_t s, int32_t t, bool grad,
+            bool full_range, const Request *forced, Prepared &X, TuneChoice &tc)
 {
     int rc = validate(n, m, arcs, p_host, s, t);
     if (rc) return rc;
     rc = current_device(X.D);
     if (rc) return rc;
-    make_plan(n, m, arcs, s, t, X.P);
+    tc = choose(X.D, graph_key(n, m, arcs, s, t), grad, forced);
+    if (tc.perm < 0 || tc.perm >= kPermKinds) tc.perm = kDefaultPerm;
+    if (!full_range) tc.perm = 0;
+    make_plan(n, m, arcs, s, t, X.P, tc.perm);
     return BAT_OK;
 }
 
-// Synchronous driver over host p; fills res (ncol doubles pairs) and count.
+// Synchronous driver over host p; fills res (ncol double-double pairs),
+// count and the plan's arc -> counter bit map (for the gradient columns).
 int run_sync(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t, u64 c_lo,
-             u64 c_hi, bool grad, std::vector<double> &res, u64 &count, Request *tmpl = nullptr)
+             u64 c_hi, bool grad, std::vector<double> &res, u64 &count, Request *tmpl = nullptr,
+             std::vector<int> *cb_of_arc = nullptr)
 {
     Prepared X;
-    int rc = prepare(n, m, arcs, p, s, t, X);
-    if (rc) return rc;
+    TuneChoice tc;
+    const bool full = c_lo == 0 && c_hi == (1ull << m);
     if (!p && m > 0) return fail(BAT_EINVAL, "p is NULL");
+    // any arc order for a whole sweep; a partial range is in the paper's
+    // order unless the caller (the autotuner timing a sample) forces one
+    const bool allow_perm = full || (tmpl && tmpl->force_perm >= 0);
+    int rc = prepare(n, m, arcs, p, s, t, grad, allow_perm, tmpl, X, tc);
+    if (rc) return rc;
     rc = thread_stream(X.D.id, X.stream);
     if (rc) return rc;
     double *p_dev = nullptr;
@@ -579,7 +719,7 @@ int run_sync(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t
     rq.n = n; rq.m = m; rq.s = s; rq.t = t; rq.arcs = arcs; rq.p_dev = p_dev;
     rq.c_lo = c_lo; rq.c_hi = c_hi; rq.grad = grad;
     Launch L;
-    rc = queue_sweep(rq, X.P, X.D, X.stream, L);
+    rc = queue_sweep(rq, X.P, X.D, tc, X.stream, L);
     if (rc) {
         (void)hipFreeAsync(p_dev, X.stream);
         if (L.ws) (void)hipFreeAsync(L.ws, X.stream);
@@ -595,13 +735,15 @@ int run_sync(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t
     HIPCHK(hipFreeAsync(p_dev, X.stream));
     HIPCHK(hipStreamSynchronize(X.stream));
     if (st) return fail(BAT_EINVAL, "a probability is outside [0,1]");
+    if (cb_of_arc) *cb_of_arc = X.P.cb_of_arc;
     return BAT_OK;
 }
 
-void split_grad(const std::vector<double> &res, int32_t m, double *dRdp, double *T1, double *T0)
+void split_grad(const std::vector<double> &res, const std::vector<int> &cb_of_arc, int32_t m, double *dRdp,
+                double *T1, double *T0)
 {
     for (int32_t a = 0; a < m; ++a) {
-        int cb = m - 1 - a;
+        int cb = cb_of_arc[a];
         const double *t0 = &res[2 * (1 + 2 * cb)], *t1 = &res[2 * (1 + 2 * cb + 1)];
         if (dRdp) dRdp[a] = (t1[0] - t0[0]) + (t1[1] - t0[1]);
         if (T1) T1[a] = t1[0] + t1[1];
@@ -656,12 +798,13 @@ int bat_reliability_grad(int32_t n, int32_t m, const bat_arc *arcs, const double
     if (!R_out || !count_out || (!dRdp_out && m > 0)) return fail(BAT_EINVAL, "NULL output pointer");
     if (m < 0 || m > BAT_MAX_ARCS) return validate(n, m, arcs, p, s, t);
     std::vector<double> res;
+    std::vector<int> cba;
     u64 cnt = 0;
-    int rc = run_sync(n, m, arcs, p, s, t, 0, 1ull << m, true, res, cnt);
+    int rc = run_sync(n, m, arcs, p, s, t, 0, 1ull << m, true, res, cnt, nullptr, &cba);
     if (rc) return rc;
     *R_out = res[0] + res[1];
     *count_out = cnt;
-    split_grad(res, m, dRdp_out, T1_out, T0_out);
+    split_grad(res, cba, m, dRdp_out, T1_out, T0_out);
     return BAT_OK;
 }
 
@@ -686,13 +829,16 @@ int bat_reliability_range(int32_t n, int32_t m, const bat_arc *arcs, const doubl
         return BAT_OK;
     }
     std::vector<double> res;
+    std::vector<int> cba;
     u64 cnt = 0;
-    int rc = run_sync(n, m, arcs, p, s, t, c_lo, c_hi, grad, res, cnt);
+    Request paper_order{};
+    paper_order.force_perm = 0;  // indices are the paper's backward order
+    int rc = run_sync(n, m, arcs, p, s, t, c_lo, c_hi, grad, res, cnt, &paper_order, &cba);
     if (rc) return rc;
     *R_hi = res[0];
     *R_lo = res[1];
     *count_out = cnt;
-    if (grad) split_grad(res, m, nullptr, T1_out, T0_out);
+    if (grad) split_grad(res, cba, m, nullptr, T1_out, T0_out);
     return BAT_OK;
 }
 
@@ -704,20 +850,21 @@ static int async_common(int32_t n, int32_t m, const bat_arc *arcs, const double 
     if (!R_dev || !count_dev || (grad && !dRdp_dev && m > 0)) return fail(BAT_EINVAL, "NULL output pointer");
     if (m > 0 && !p_dev) return fail(BAT_EINVAL, "p_dev is NULL");
     Prepared X;
-    int rc = prepare(n, m, arcs, nullptr, s, t, X);
+    TuneChoice tc;
+    int rc = prepare(n, m, arcs, nullptr, s, t, grad, true, nullptr, X, tc);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     Request rq{};
     rq.n = n; rq.m = m; rq.s = s; rq.t = t; rq.arcs = arcs; rq.p_dev = p_dev;
     rq.c_lo = 0; rq.c_hi = 1ull << m; rq.grad = grad;
     Launch L;
-    rc = queue_sweep(rq, X.P, X.D, st, L);
+    rc = queue_sweep(rq, X.P, X.D, tc, st, L);
     if (rc) {
         if (L.ws) (void)hipFreeAsync(L.ws, st);
         return rc;
     }
-    HIPCHK(batk::finalize(st, (const double *)L.res, (const u64 *)L.count, (const int *)L.status, (u32)m, grad,
-                          R_dev, (u64 *)count_dev, dRdp_dev, T1_dev, T0_dev, (int *)status_dev));
+    HIPCHK(batk::finalize(st, (const double *)L.res, (const u64 *)L.count, (const int *)L.status, L.cb_of_arc,
+                          (u32)m, grad, R_dev, (u64 *)count_dev, dRdp_dev, T1_dev, T0_dev, (int *)status_dev));
     HIPCHK(hipFreeAsync(L.ws, st));
     return BAT_OK;
 }
@@ -755,61 +902,70 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
                  double *best_ns_per_vector)
 {
     t_err.clear();
-    Prepared X;
-    int rc = prepare(n, m, arcs, p, s, t, X);
+    int rc = validate(n, m, arcs, p, s, t);
     if (rc) return rc;
     if (!p && m > 0) return fail(BAT_EINVAL, "p is NULL");
-    // sample: 8 ranges spread evenly over the counter, ~2^31 vectors in all
+    DeviceInfo D;
+    rc = current_device(D);
+    if (rc) return rc;
+    // Each candidate sweeps a sample of its work items spread over the whole
+    // counter (an odd-multiplier hash of the item index, so every arc's
+    // state varies across the sample), about 2^37 vectors or everything if
+    // that is less; candidates are compared by time per vector.
     const u64 total = 1ull << m;
-    const int nslice = total >= (1ull << 16) ? 8 : 1;
-    const u64 want = std::min<u64>(total, 1ull << 31);
-    const u64 len = std::max<u64>(want / nslice, 1);
-    std::vector<std::pair<u64, u64>> ranges;
-    for (int i = 0; i < nslice; ++i) {
-        u64 lo = (total / nslice) * i;
-        ranges.push_back({lo, std::min(total, lo + len)});
+    const u32 ubits = m > bat::kWordBits ? (u32)m - bat::kWordBits : 0u;
+    // the automatic work-item size (as queue_sweep picks it)
+    int clog_auto = 0;
+    {
+        u64 target = (1ull << ubits) / ((u64)std::max(D.cus, 1) * 64ull);
+        while (clog_auto < 12 && (2ull << clog_auto) <= target) ++clog_auto;
     }
-    struct Cand { int clog, check, jit; };
-    std::vector<Cand> cands;
-    for (int jit : {0, 1})
-        for (int check : {1, 2})
-            for (int clog : {8, 10, 12}) cands.push_back({clog, check, jit});
-    double best = 1e300;
-    Cand bc{0, 1, 2};
-    for (const Cand &c : cands) {
-        double ms = 0.0;
-        bool ok = true;
-        for (int rep = 0; rep < 2 && ok; ++rep) {  // first pass warms the JIT cache
-            ms = 0.0;
-            for (auto &r : ranges) {
-                Request tmpl{};
-                tmpl.force_chunk_log2 = c.clog;
-                tmpl.force_check = c.check;
-                tmpl.force_jit = c.jit;
-                std::vector<double> res;
-                u64 cnt = 0;
-                if (run_sync(n, m, arcs, p, s, t, r.first, r.second, false, res, cnt, &tmpl)) {
-                    ok = false;
-                    break;
-                }
-                bat_launch_info li;
-                if (bat_last_launch(&li)) { ok = false; break; }
-                ms += li.kernel_ms;
-            }
+    struct Cand { int clog, check, jit, perm; };
+    auto measure = [&](const Cand &c, double &ns) -> bool {
+        for (int rep = 0; rep < 2; ++rep) {  // the first pass warms the JIT cache
+            Request tmpl{};
+            tmpl.force_chunk_log2 = c.clog;
+            tmpl.force_check = c.check;
+            tmpl.force_jit = c.jit;
+            tmpl.force_perm = c.perm;
+            const int cl = c.clog > 0 ? c.clog : std::max(clog_auto, 3);
+            const u64 per_item = 1ull << (cl + bat::kWordBits);
+            tmpl.sample_items = std::max<u64>(1024, (1ull << 37) / per_item);
+            std::vector<double> res;
+            u64 cnt = 0;
+            bat_launch_info li;
+            if (run_sync(n, m, arcs, p, s, t, 0, total, false, res, cnt, &tmpl) || bat_last_launch(&li)) return false;
+            ns = li.kernel_ms * 1e6 / (double)li.vectors;
         }
-        if (ok && ms < best) {
-            best = ms;
+        return true;
+    };
+    double best = 1e300;
+    Cand bc{0, 1, 2, kDefaultPerm};
+    auto consider = [&](const Cand &c) {
+        double ns;
+        if (measure(c, ns) && ns < best) {
+            best = ns;
             bc = c;
         }
+    };
+    // stage 1: arc-to-bit order with the specialised kernel, automatic size
+    for (int perm = 0; perm < kPermKinds; ++perm) consider({0, 1, 1, perm});
+    // stage 2: work-item size, convergence-test cadence, generic kernel
+    const Cand w = bc;
+    for (int d : {-2, 2}) {
+        int cl = clog_auto + d;
+        if (cl >= 3 && cl <= 14) consider({cl, w.check, w.jit, w.perm});
     }
-    u64 sampled = 0;
-    for (auto &r : ranges) sampled += r.second - r.first;
-    if (best_ns_per_vector) *best_ns_per_vector = best * 1e6 / (double)sampled;
+    consider({bc.clog, 2, bc.jit, bc.perm});
+    if (total <= (1ull << 32)) consider({bc.clog, 1, 0, 0});
+    if (best >= 1e300) return fail(BAT_EDEVICE, "autotune: no candidate ran (%s)", t_err.c_str());
+    if (best_ns_per_vector) *best_ns_per_vector = best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        TuneChoice tc{bc.clog, bc.check, bc.jit};
-        g_tune[std::to_string(X.D.id) + " fwd " + X.P.structure] = tc;
-        g_tune[std::to_string(X.D.id) + " grad " + X.P.structure] = tc;
+        TuneChoice tc{bc.clog, bc.check, bc.jit, bc.perm};
+        const std::string gk = graph_key(n, m, arcs, s, t);
+        g_tune[std::to_string(D.id) + " fwd " + gk] = tc;
+        g_tune[std::to_string(D.id) + " grad " + gk] = tc;
     }
     t_err.clear();
     return BAT_OK;

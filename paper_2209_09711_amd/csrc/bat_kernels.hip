@@ -87,16 +87,23 @@ __device__ void build_tables_dev(const double *__restrict__ p, u32 m, u32 f, dou
 }
 
 // One block of 256 threads for the single-graph sweeps; also checks p.
+// row[j] (nullable = identity) is the arc whose probability plays the role
+// of arc j of the identity order, i.e. the arc at counter bit m-1-j.
 extern "C" __global__ void __launch_bounds__(256)
-k_build_tables(const double *__restrict__ p, u32 m, u32 f, double *__restrict__ T, int *status)
+k_build_tables(const double *__restrict__ p, const unsigned char *__restrict__ row, u32 m, u32 f,
+               double *__restrict__ T, int *status)
 {
-    if (threadIdx.x == 0) {
+    __shared__ double pr[64];
+    const u32 tid = threadIdx.x;
+    if (tid < m) pr[tid] = row ? p[row[tid]] : p[tid];
+    if (tid == 0) {
         int st = 0;
         for (u32 i = 0; i < m; ++i)
             if (!(p[i] >= 0.0 && p[i] <= 1.0)) st = -1;
         *status = st;
     }
-    build_tables_dev(p, m, f, T, true);
+    __syncthreads();
+    build_tables_dev(pr, m, f, T, true);
 }
 
 template <int NMAX>
@@ -159,11 +166,12 @@ k_reduce(const double *__restrict__ part, const u64 *__restrict__ pcount, u64 n_
     }
 }
 
-// Write R, count and (if requested) T1/T0/dR/dp in arc order; counter bit
-// cb belongs to arc m-1-cb.  Invalid probabilities give NaN and status -1.
+// Write R, count and (if requested) T1/T0/dR/dp in arc order; arc a sits at
+// counter bit cb_of_arc[a] (nullable = identity, m-1-a).  Invalid probabilities give NaN and status -1.
 extern "C" __global__ void __launch_bounds__(64)
 k_finalize(const double *__restrict__ res, const u64 *__restrict__ count, const int *__restrict__ status,
-           u32 m, u32 grad, double *R, u64 *cnt, double *dRdp, double *T1, double *T0, int *status_out)
+           const unsigned char *__restrict__ cb_of_arc, u32 m, u32 grad, double *R, u64 *cnt, double *dRdp,
+           double *T1, double *T0, int *status_out)
 {
     const u32 tid = threadIdx.x;
     const int st = *status;
@@ -175,7 +183,7 @@ k_finalize(const double *__restrict__ res, const u64 *__restrict__ count, const 
     }
     if (grad) {
         for (u32 a = tid; a < m; a += blockDim.x) {
-            u32 cb = m - 1 - a;
+            u32 cb = cb_of_arc ? cb_of_arc[a] : m - 1 - a;
             const double *t0 = res + 2 * (1 + 2 * cb), *t1 = res + 2 * (1 + 2 * cb + 1);
             double g = (t1[0] - t0[0]) + (t1[1] - t0[1]);
             if (dRdp) dRdp[a] = st ? nan : g;
@@ -349,9 +357,10 @@ k_batched_reduce(const batk::BatchEntry *__restrict__ entries, const double *__r
 // ------------------------------------------------------------ launchers
 namespace batk {
 
-hipError_t build_tables(hipStream_t st, const double *p, u32 m, u32 f, double *T, int *status)
+hipError_t build_tables(hipStream_t st, const double *p, const unsigned char *row, u32 m, u32 f, double *T,
+                        int *status)
 {
-    hipLaunchKernelGGL(k_build_tables, dim3(1), dim3(256), 0, st, p, m, f, T, status);
+    hipLaunchKernelGGL(k_build_tables, dim3(1), dim3(256), 0, st, p, row, m, f, T, status);
     return hipGetLastError();
 }
 
@@ -378,11 +387,12 @@ hipError_t reduce(hipStream_t st, const double *part, const u64 *pcount, u64 n_c
     return hipGetLastError();
 }
 
-hipError_t finalize(hipStream_t st, const double *res, const u64 *count, const int *status, u32 m, bool grad,
-                    double *R, u64 *cnt, double *dRdp, double *T1, double *T0, int *status_out)
+hipError_t finalize(hipStream_t st, const double *res, const u64 *count, const int *status,
+                    const unsigned char *cb_of_arc, u32 m, bool grad, double *R, u64 *cnt, double *dRdp, double *T1,
+                    double *T0, int *status_out)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, res, count, status, m, grad ? 1u : 0u, R, cnt, dRdp,
-                       T1, T0, status_out);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, res, count, status, cb_of_arc, m, grad ? 1u : 0u, R,
+                       cnt, dRdp, T1, T0, status_out);
     return hipGetLastError();
 }
 

@@ -43,11 +43,13 @@ hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, const BatchP
 hipError_t batched_reduce(hipStream_t st, const BatchEntry *entries, unsigned n_entries, const double *part,
                           const bat::u64 *pcount, bat::u32 n_pvec, double *R, bat::u64 *counts);
 
-hipError_t build_tables(hipStream_t st, const double *p, bat::u32 m, bat::u32 f, double *T, int *status);
+hipError_t build_tables(hipStream_t st, const double *p, const unsigned char *row, bat::u32 m, bat::u32 f,
+                        double *T, int *status);
 hipError_t sweep_dyn(hipStream_t st, unsigned blocks, bool grad, int nmax, const bat::KParams &K);
 hipError_t reduce(hipStream_t st, const double *part, const bat::u64 *pcount, bat::u64 n_chunks, bat::u32 ncol,
                   double *res, bat::u64 *count);
-hipError_t finalize(hipStream_t st, const double *res, const bat::u64 *count, const int *status, bat::u32 m,
-                    bool grad, double *R, bat::u64 *cnt, double *dRdp, double *T1, double *T0, int *status_out);
+hipError_t finalize(hipStream_t st, const double *res, const bat::u64 *count, const int *status,
+                    const unsigned char *cb_of_arc, bat::u32 m, bool grad, double *R, bat::u64 *cnt, double *dRdp,
+                    double *T1, double *T0, int *status_out);
 
 }  // namespace batk

@@ -360,6 +360,26 @@ def test_ragged_ranges_specialised_vs_oracle(seed):
             assert np.allclose(r.T0, o.T0, rtol=1e-12, atol=1e-300)
 
 
+@pytest.mark.parametrize("perm", [0, 1, 2, 3])
+def test_arc_to_bit_orders(perm):
+    """Every arc -> counter-bit order gives the same count, R and gradient
+    (a whole sweep is a sum over all vectors; only the work split changes)."""
+    B = _B()
+    nets = [W.random_connected(15, 30, seed=90, p_lo=0.4, p_hi=0.99), W.config4(),
+            W.random_connected(10, 20, seed=91, p_lo=0.1, p_hi=0.9)]
+    nets[2].arcs = nets[2].arcs + [(0, 0), (3, 3)]               # pruned self-loops
+    nets[2].p = np.concatenate([nets[2].p, [0.3, 0.8]])
+    for net in nets:
+        say("perm", perm, net.name)
+        with options(BAT_PERM=0, BAT_JIT=1):
+            ref = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+        with options(BAT_PERM=perm, BAT_JIT=1):
+            g = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+            R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+        assert g.count == ref.count == cnt and rel_ok(g.R, ref.R) and rel_ok(R, ref.R)
+        assert np.allclose(g.T1, ref.T1, rtol=1e-12, atol=0) and np.allclose(g.T0, ref.T0, rtol=1e-12, atol=0)
+
+
 def test_autotune_choice_keeps_results():
     B = _B()
     net = W.random_connected(16, 34, seed=8, p_lo=0.6, p_hi=0.99)
