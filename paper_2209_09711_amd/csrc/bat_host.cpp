@@ -910,8 +910,9 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
     if (rc) return rc;
     // Each candidate sweeps a sample of its work items spread over the whole
     // counter (an odd-multiplier hash of the item index, so every arc's
-    // state varies across the sample), about 2^37 vectors or everything if
-    // that is less; candidates are compared by time per vector.
+    // state varies across the sample), about 2^38 vectors or everything if
+    // that is less; candidates are compared by their best time per vector
+    // over two timed passes.
     const u64 total = 1ull << m;
     const u32 ubits = m > bat::kWordBits ? (u32)m - bat::kWordBits : 0u;
     // the automatic work-item size (as queue_sweep picks it)
@@ -922,7 +923,8 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
     }
     struct Cand { int clog, check, jit, perm; };
     auto measure = [&](const Cand &c, double &ns) -> bool {
-        for (int rep = 0; rep < 2; ++rep) {  // the first pass warms the JIT cache
+        ns = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {  // the first pass warms the JIT cache
             Request tmpl{};
             tmpl.force_chunk_log2 = c.clog;
             tmpl.force_check = c.check;
@@ -930,12 +932,12 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
             tmpl.force_perm = c.perm;
             const int cl = c.clog > 0 ? c.clog : std::max(clog_auto, 3);
             const u64 per_item = 1ull << (cl + bat::kWordBits);
-            tmpl.sample_items = std::max<u64>(1024, (1ull << 37) / per_item);
+            tmpl.sample_items = std::max<u64>(1024, (1ull << 38) / per_item);
             std::vector<double> res;
             u64 cnt = 0;
             bat_launch_info li;
             if (run_sync(n, m, arcs, p, s, t, 0, total, false, res, cnt, &tmpl) || bat_last_launch(&li)) return false;
-            ns = li.kernel_ms * 1e6 / (double)li.vectors;
+            if (rep > 0) ns = std::min(ns, li.kernel_ms * 1e6 / (double)li.vectors);
         }
         return true;
     };
