@@ -64,7 +64,7 @@ int fail(int code, const char *fmt, ...)
 
 // ------------------------------------------------------------ options
 struct Options {
-    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1};
+    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -77,6 +77,7 @@ struct Options {
         rd("BAT_CHECK_EVERY", check_every);
         rd("BAT_AUTOTUNE", autotune);
         rd("BAT_PERM", perm);
+        rd("BAT_CHAIN_LOG2", chain_log2);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -87,6 +88,7 @@ struct Options {
         if (!strcmp(k, "BAT_CHECK_EVERY")) return &check_every;
         if (!strcmp(k, "BAT_AUTOTUNE")) return &autotune;
         if (!strcmp(k, "BAT_PERM")) return &perm;
+        if (!strcmp(k, "BAT_CHAIN_LOG2")) return &chain_log2;
         return nullptr;
     }
 };
@@ -408,12 +410,13 @@ std::string jit_source(const Plan &P, bool grad)
     arr("RV", P.rv);
     arr("RB", P.rb);
     arr("RD", P.rd);
-    // relaxations of counter bits 11, 12, 13 (the chained iteration arcs)
-    int ck[3] = {-1, -1, -1};
+    // relaxations of counter bits 11..15 (the chained iteration arcs)
+    int ck[5] = {-1, -1, -1, -1, -1};
     for (size_t k = 0; k < nr; ++k)
-        if (P.rb[k] >= bat::kWordBits && P.rb[k] < bat::kWordBits + 3) ck[P.rb[k] - bat::kWordBits] = (int)k;
-    s += "  static constexpr int CK[3] = {" + std::to_string(ck[0]) + "," + std::to_string(ck[1]) + "," +
-         std::to_string(ck[2]) + "};\n";
+        if (P.rb[k] >= bat::kWordBits && P.rb[k] < bat::kWordBits + 5) ck[P.rb[k] - bat::kWordBits] = (int)k;
+    s += "  static constexpr int CK[5] = {";
+    for (int b = 0; b < 5; ++b) s += (b ? "," : "") + std::to_string(ck[b]);
+    s += "};\n";
     s += "};\n";
     if (grad)
         s += "extern \"C\" __global__ void __launch_bounds__(256) bat_grad_jit(bat::KParams P) {\n"
@@ -468,7 +471,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, do
 
 // ------------------------------------------------------------ autotune cache
 struct TuneChoice {
-    int chunk_log2, check_every, jit, perm;
+    int chunk_log2, check_every, jit, perm, chain = -1;
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneChoice> g_tune;
@@ -490,7 +493,7 @@ struct Request {
     u64 c_lo, c_hi;
     bool grad;
     // forced knobs (autotuner); -1 = from options / the tuned choice
-    int force_chunk_log2 = -1, force_check = -1, force_jit = -1, force_perm = -1;
+    int force_chunk_log2 = -1, force_check = -1, force_jit = -1, force_perm = -1, force_chain = -1;
     // timing sample (autotuner): sweep only this many work items, spread
     // over the whole counter by an odd multiplier (0 = everything)
     u64 sample_items = 0;
@@ -508,11 +511,13 @@ TuneChoice choose(const DeviceInfo &D, const std::string &gkey, bool grad, const
         if (it != g_tune.end()) tc = it->second;
     }
     if (O.perm.load() >= 0) tc.perm = (int)O.perm.load();
+    if (O.chain_log2.load() >= 0) tc.chain = (int)O.chain_log2.load();
     if (rq) {
         if (rq->force_chunk_log2 >= 0) tc.chunk_log2 = rq->force_chunk_log2;
         if (rq->force_check >= 0) tc.check_every = rq->force_check;
         if (rq->force_jit >= 0) tc.jit = rq->force_jit;
         if (rq->force_perm >= 0) tc.perm = rq->force_perm;
+        if (rq->force_chain >= 0) tc.chain = rq->force_chain;
     }
     return tc;
 }
@@ -542,10 +547,15 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     bool use_jit = false;
     if (tc.jit == 1) use_jit = true;
     else if (tc.jit == 2) use_jit = (rq.c_hi - rq.c_lo) >= (1ull << 32) || (P.N > 32 && (rq.c_hi - rq.c_lo) >= (1ull << 22));
-    // warm-started chains need the specialised closure and >= 3 iteration bits
-    const bool chain = use_jit && ubits >= 3 && !P.ru.empty();
-    const u64 g_base = chain ? (g_first & ~7ull) : g_first;
-    const u64 g_end = chain ? (g_last | 7ull) : g_last;
+    // warm-started chains need the specialised closure and >= k iteration
+    // bits; k = 3 or 5 (the gradient sweep keeps at most 4 fast bits: k = 3)
+    u32 ck = tc.chain < 0 ? 3u : (tc.chain >= 5 ? 5u : (tc.chain >= 3 ? 3u : 0u));
+    if (rq.grad && ck > 3) ck = 3;
+    if (ubits < ck) ck = ubits >= 3 ? 3u : 0u;
+    const bool chain = use_jit && ck > 0 && !P.ru.empty();
+    const u64 bmask = chain ? (1ull << ck) - 1ull : 0ull;
+    const u64 g_base = g_first & ~bmask;
+    const u64 g_end = g_last | bmask;
     const u64 iters = g_end - g_base + 1;
 
     int clog = tc.chunk_log2;
@@ -555,10 +565,10 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
         while (clog < 12 && (2ull << clog) <= target) ++clog;
     }
     clog = std::min(clog, 20);
-    if (chain) clog = std::max(clog, 3);
+    if (chain) clog = std::max(clog, (int)ck);
     u32 f = (u32)std::max<int64_t>(0, std::min<int64_t>(O.seg_log2.load(), bat::kMaxSegLog));
     if (rq.grad) f = std::min<u32>(f, bat::kGradFastMax);
-    if (chain) f = std::max<u32>(f, 3);
+    if (chain) f = std::max<u32>(f, ck);
     if (f > ubits) f = ubits;
 
     bat::KParams K;
@@ -582,7 +592,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     K.ubits = ubits;
     K.seg_log = f;
     K.check_every = tc.check_every >= 2 ? 2u : 1u;
-    K.chain = chain ? 1u : 0u;
+    K.chain = chain ? ck : 0u;
     K.ncol = rq.grad ? 1u + 2u * m : 1u;
     K.n_nodes = (u32)P.N;
     K.s = (u32)P.S;
@@ -921,7 +931,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         u64 target = (1ull << ubits) / ((u64)std::max(D.cus, 1) * 64ull);
         while (clog_auto < 12 && (2ull << clog_auto) <= target) ++clog_auto;
     }
-    struct Cand { int clog, check, jit, perm; };
+    struct Cand { int clog, check, jit, perm, chain; };
     auto measure = [&](const Cand &c, double &ns) -> bool {
         ns = 1e300;
         for (int rep = 0; rep < 3; ++rep) {  // the first pass warms the JIT cache
@@ -930,6 +940,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
             tmpl.force_check = c.check;
             tmpl.force_jit = c.jit;
             tmpl.force_perm = c.perm;
+            tmpl.force_chain = c.chain;
             const int cl = c.clog > 0 ? c.clog : std::max(clog_auto, 3);
             const u64 per_item = 1ull << (cl + bat::kWordBits);
             tmpl.sample_items = std::max<u64>(1024, (1ull << 38) / per_item);
@@ -942,7 +953,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         return true;
     };
     double best = 1e300;
-    Cand bc{0, 1, 2, kDefaultPerm};
+    Cand bc{0, 1, 2, kDefaultPerm, 3};
     auto consider = [&](const Cand &c) {
         double ns;
         if (measure(c, ns) && ns < best) {
@@ -950,21 +961,23 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
             bc = c;
         }
     };
-    // stage 1: arc-to-bit order with the specialised kernel, automatic size
-    for (int perm = 0; perm < kPermKinds; ++perm) consider({0, 1, 1, perm});
+    // stage 1: arc-to-bit order x chain length, specialised kernel,
+    // automatic work-item size (the two interact)
+    for (int perm = 0; perm < kPermKinds; ++perm)
+        for (int k : {3, 5}) consider({0, 1, 1, perm, k});
     // stage 2: work-item size, convergence-test cadence, generic kernel
     const Cand w = bc;
     for (int d : {-2, 2}) {
         int cl = clog_auto + d;
-        if (cl >= 3 && cl <= 14) consider({cl, w.check, w.jit, w.perm});
+        if (cl >= 5 && cl <= 14) consider({cl, w.check, w.jit, w.perm, w.chain});
     }
-    consider({bc.clog, 2, bc.jit, bc.perm});
-    if (total <= (1ull << 32)) consider({bc.clog, 1, 0, 0});
+    consider({bc.clog, 2, bc.jit, bc.perm, bc.chain});
+    if (total <= (1ull << 32)) consider({bc.clog, 1, 0, 0, 0});
     if (best >= 1e300) return fail(BAT_EDEVICE, "autotune: no candidate ran (%s)", t_err.c_str());
     if (best_ns_per_vector) *best_ns_per_vector = best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        TuneChoice tc{bc.clog, bc.check, bc.jit, bc.perm};
+        TuneChoice tc{bc.clog, bc.check, bc.jit, bc.perm, bc.chain};
         const std::string gk = graph_key(n, m, arcs, s, t);
         g_tune[std::to_string(D.id) + " fwd " + gk] = tc;
         g_tune[std::to_string(D.id) + " grad " + gk] = tc;

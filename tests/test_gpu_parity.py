@@ -380,6 +380,27 @@ def test_arc_to_bit_orders(perm):
         assert np.allclose(g.T1, ref.T1, rtol=1e-12, atol=0) and np.allclose(g.T0, ref.T0, rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("k", [0, 3, 5])
+def test_chain_lengths(k):
+    """Warm-start chain lengths: whole sweeps agree with the frontier DP, and
+    ranges that cut blocks of 2^k iterations agree with the oracle."""
+    B = _B()
+    rng = np.random.default_rng(k)
+    net = W.config4()
+    with options(BAT_CHAIN_LOG2=k, BAT_JIT=1):
+        say("chain", k, net.name)
+        R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+        Rd, cd = frontier_dp.reliability(net.n, net.arcs, net.p, net.s, net.t)
+        assert cnt == cd and rel_ok(R, Rd)
+        small = W.random_connected(13, 26, seed=77 + k, p_lo=0.3, p_hi=0.99)
+        for _ in range(3):
+            lo = int(rng.integers(0, (1 << small.m) - (1 << 19)))
+            hi = lo + int(rng.integers(1, 1 << 19))
+            r = B.bat_reliability_range(small.n, small.arcs, small.p, small.s, small.t, lo, hi)
+            o = oracle.reliability_range(small.n, small.arcs, small.p, small.s, small.t, lo, hi)
+            assert r.count == o.count and rel_ok(r.R, o.sum)
+
+
 def test_autotune_choice_keeps_results():
     B = _B()
     net = W.random_connected(16, 34, seed=8, p_lo=0.6, p_hi=0.99)
