@@ -161,11 +161,18 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
  *                      the chained iteration bits (R and counts never
  *                      depend on it; the range entry point always uses the
  *                      paper's order)
- *   "BAT_CHAIN_LOG2"   -1 = tuned (else 3), 0 = no warm starts, 3 or 5: the
+ *   "BAT_CHAIN_LOG2"   -1 = tuned (else 3), 0 = no warm starts, 3..6: the
  *                      specialised forward sweep visits iterations in blocks
  *                      of 2^k along chains that switch one iteration arc on
  *                      per step, starting each step's closure from the
- *                      previous one (gradient sweeps use at most 3)
+ *                      previous one (gradient sweeps use at most 4)
+ *   "BAT_ITEM_ORDER"   which counter chunk each wavefront work item sweeps:
+ *                      -1 or 1 = spread (item i takes chunk i times an odd
+ *                      constant, modulo the chunk count, when that count is
+ *                      a power of two, so work items running side by side
+ *                      cover distant parts of the counter), 0 = counter
+ *                      order; R and counts never depend on it beyond
+ *                      floating-point rounding
  * Unknown keys return BAT_EINVAL.
  */
 int bat_set_option(const char *key, int64_t value);

@@ -64,7 +64,7 @@ int fail(int code, const char *fmt, ...)
 
 // ------------------------------------------------------------ options
 struct Options {
-    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1};
+    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -78,6 +78,7 @@ struct Options {
         rd("BAT_AUTOTUNE", autotune);
         rd("BAT_PERM", perm);
         rd("BAT_CHAIN_LOG2", chain_log2);
+        rd("BAT_ITEM_ORDER", item_order);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -89,6 +90,7 @@ struct Options {
         if (!strcmp(k, "BAT_AUTOTUNE")) return &autotune;
         if (!strcmp(k, "BAT_PERM")) return &perm;
         if (!strcmp(k, "BAT_CHAIN_LOG2")) return &chain_log2;
+        if (!strcmp(k, "BAT_ITEM_ORDER")) return &item_order;
         return nullptr;
     }
 };
@@ -410,12 +412,12 @@ std::string jit_source(const Plan &P, bool grad)
     arr("RV", P.rv);
     arr("RB", P.rb);
     arr("RD", P.rd);
-    // relaxations of counter bits 11..15 (the chained iteration arcs)
-    int ck[5] = {-1, -1, -1, -1, -1};
+    // relaxations of counter bits 11..16 (the chained iteration arcs)
+    int ck[6] = {-1, -1, -1, -1, -1, -1};
     for (size_t k = 0; k < nr; ++k)
-        if (P.rb[k] >= bat::kWordBits && P.rb[k] < bat::kWordBits + 5) ck[P.rb[k] - bat::kWordBits] = (int)k;
-    s += "  static constexpr int CK[5] = {";
-    for (int b = 0; b < 5; ++b) s += (b ? "," : "") + std::to_string(ck[b]);
+        if (P.rb[k] >= bat::kWordBits && P.rb[k] < bat::kWordBits + 6) ck[P.rb[k] - bat::kWordBits] = (int)k;
+    s += "  static constexpr int CK[6] = {";
+    for (int b = 0; b < 6; ++b) s += (b ? "," : "") + std::to_string(ck[b]);
     s += "};\n";
     s += "};\n";
     if (grad)
@@ -471,7 +473,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, do
 
 // ------------------------------------------------------------ autotune cache
 struct TuneChoice {
-    int chunk_log2, check_every, jit, perm, chain = -1;
+    int chunk_log2, check_every, jit, perm, chain = -1, order = -1;
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneChoice> g_tune;
@@ -493,7 +495,8 @@ struct Request {
     u64 c_lo, c_hi;
     bool grad;
     // forced knobs (autotuner); -1 = from options / the tuned choice
-    int force_chunk_log2 = -1, force_check = -1, force_jit = -1, force_perm = -1, force_chain = -1;
+    int force_chunk_log2 = -1, force_check = -1, force_jit = -1, force_perm = -1, force_chain = -1,
+        force_order = -1;
     // timing sample (autotuner): sweep only this many work items, spread
     // over the whole counter by an odd multiplier (0 = everything)
     u64 sample_items = 0;
@@ -512,12 +515,14 @@ TuneChoice choose(const DeviceInfo &D, const std::string &gkey, bool grad, const
     }
     if (O.perm.load() >= 0) tc.perm = (int)O.perm.load();
     if (O.chain_log2.load() >= 0) tc.chain = (int)O.chain_log2.load();
+    if (O.item_order.load() >= 0) tc.order = (int)O.item_order.load();
     if (rq) {
         if (rq->force_chunk_log2 >= 0) tc.chunk_log2 = rq->force_chunk_log2;
         if (rq->force_check >= 0) tc.check_every = rq->force_check;
         if (rq->force_jit >= 0) tc.jit = rq->force_jit;
         if (rq->force_perm >= 0) tc.perm = rq->force_perm;
         if (rq->force_chain >= 0) tc.chain = rq->force_chain;
+        if (rq->force_order >= 0) tc.order = rq->force_order;
     }
     return tc;
 }
@@ -548,9 +553,9 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     if (tc.jit == 1) use_jit = true;
     else if (tc.jit == 2) use_jit = (rq.c_hi - rq.c_lo) >= (1ull << 32) || (P.N > 32 && (rq.c_hi - rq.c_lo) >= (1ull << 22));
     // warm-started chains need the specialised closure and >= k iteration
-    // bits; k = 3 or 5 (the gradient sweep keeps at most 4 fast bits: k = 3)
-    u32 ck = tc.chain < 0 ? 3u : (tc.chain >= 5 ? 5u : (tc.chain >= 3 ? 3u : 0u));
-    if (rq.grad && ck > 3) ck = 3;
+    // bits; k = 3..6 (the gradient sweep keeps at most 4 fast bits: k <= 4)
+    u32 ck = tc.chain < 0 ? 3u : (tc.chain >= 6 ? 6u : (tc.chain >= 3 ? (u32)tc.chain : 0u));
+    if (rq.grad && ck > (u32)bat::kGradFastMax) ck = bat::kGradFastMax;
     if (ubits < ck) ck = ubits >= 3 ? 3u : 0u;
     const bool chain = use_jit && ck > 0 && !P.ru.empty();
     const u64 bmask = chain ? (1ull << ck) - 1ull : 0ull;
@@ -583,10 +588,14 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     K.n_chunks = (iters + K.chunk_iters - 1) >> clog;
     K.chunk_mul = 1;
     K.chunk_mask = ~0ull;
-    if (rq.sample_items && rq.sample_items < K.n_chunks && (K.n_chunks & (K.n_chunks - 1)) == 0) {
-        K.chunk_mul = 0x9E3779B97F4A7C15ull;  // odd: a bijection modulo n_chunks
+    const bool pow2 = (K.n_chunks & (K.n_chunks - 1)) == 0;
+    const bool sample = rq.sample_items && rq.sample_items < K.n_chunks && pow2;
+    if (pow2 && (sample || tc.order != 0)) {
+        // work item -> chunk through an odd multiplier: a bijection modulo
+        // n_chunks that spreads consecutive items over the whole counter
+        K.chunk_mul = 0x9E3779B97F4A7C15ull;
         K.chunk_mask = K.n_chunks - 1;
-        K.n_chunks = rq.sample_items;
+        if (sample) K.n_chunks = rq.sample_items;
     }
     K.m = m;
     K.ubits = ubits;
@@ -954,9 +963,15 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
     };
     double best = 1e300;
     Cand bc{0, 1, 2, kDefaultPerm, 3};
+    const char *vb = getenv("BAT_AUTOTUNE_VERBOSE");
+    const bool verbose = vb && *vb && *vb != '0';
     auto consider = [&](const Cand &c) {
         double ns;
-        if (measure(c, ns) && ns < best) {
+        const bool ok = measure(c, ns);
+        if (verbose)
+            fprintf(stderr, "bat_autotune: chunk_log2=%d check=%d jit=%d perm=%d chain=%d -> %s %.6f ns/vector\n",
+                    c.clog, c.check, c.jit, c.perm, c.chain, ok ? "ok" : "failed", ok ? ns : 0.0);
+        if (ok && ns < best) {
             best = ns;
             bc = c;
         }
@@ -965,6 +980,11 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
     // automatic work-item size (the two interact)
     for (int perm = 0; perm < kPermKinds; ++perm)
         for (int k : {3, 5}) consider({0, 1, 1, perm, k});
+    {
+        const Cand w1 = bc;
+        for (int k : {4, 6})
+            if (k != w1.chain) consider({0, 1, 1, w1.perm, k});
+    }
     // stage 2: work-item size, convergence-test cadence, generic kernel
     const Cand w = bc;
     for (int d : {-2, 2}) {

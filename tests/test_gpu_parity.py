@@ -380,7 +380,7 @@ def test_arc_to_bit_orders(perm):
         assert np.allclose(g.T1, ref.T1, rtol=1e-12, atol=0) and np.allclose(g.T0, ref.T0, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("k", [0, 3, 5])
+@pytest.mark.parametrize("k", [0, 3, 4, 5, 6])
 def test_chain_lengths(k):
     """Warm-start chain lengths: whole sweeps agree with the frontier DP, and
     ranges that cut blocks of 2^k iterations agree with the oracle."""
@@ -396,6 +396,32 @@ def test_chain_lengths(k):
         for _ in range(3):
             lo = int(rng.integers(0, (1 << small.m) - (1 << 19)))
             hi = lo + int(rng.integers(1, 1 << 19))
+            r = B.bat_reliability_range(small.n, small.arcs, small.p, small.s, small.t, lo, hi)
+            o = oracle.reliability_range(small.n, small.arcs, small.p, small.s, small.t, lo, hi)
+            assert r.count == o.count and rel_ok(r.R, o.sum)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_item_orders(order):
+    """Counter-order and spread work-item orders sweep the same vectors: equal
+    counts, R and gradient; ranges (chunk counts that are not powers of two)
+    keep agreeing with the oracle."""
+    B = _B()
+    nets = [W.config4(), W.random_connected(15, 30, seed=92, p_lo=0.4, p_hi=0.99)]
+    for net in nets:
+        say("item order", order, net.name)
+        with options(BAT_ITEM_ORDER=0, BAT_JIT=1, BAT_CHUNK_LOG2=3):
+            ref = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+        with options(BAT_ITEM_ORDER=order, BAT_JIT=1, BAT_CHUNK_LOG2=3):
+            g = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+            R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+            li = B.bat_last_launch()
+            assert li.n_chunks > 1
+        assert g.count == ref.count == cnt and rel_ok(g.R, ref.R) and rel_ok(R, ref.R)
+        assert np.allclose(g.T1, ref.T1, rtol=1e-12, atol=0) and np.allclose(g.T0, ref.T0, rtol=1e-12, atol=0)
+    small = W.random_connected(13, 26, seed=93, p_lo=0.3, p_hi=0.99)
+    with options(BAT_ITEM_ORDER=order, BAT_CHUNK_LOG2=2):
+        for lo, hi in [(12345, 12345 + 3 * (1 << 13) + 77), (0, 1 << 22), (1 << 24, (1 << 24) + (5 << 13))]:
             r = B.bat_reliability_range(small.n, small.arcs, small.p, small.s, small.t, lo, hi)
             o = oracle.reliability_range(small.n, small.arcs, small.p, small.s, small.t, lo, hi)
             assert r.count == o.count and rel_ok(r.R, o.sum)
