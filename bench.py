@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the fwd+grad / batched comparisons")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--cpu-sample-log2", type=int, default=30,
                     help="log2 of the state vectors in the oracle's timed sample")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
@@ -207,6 +208,7 @@ def main():
         out["fwd_grad_vs_fwd"] = {"workload": "random n=18 m=36 (seed 220909711/4), R + 36 gradients",
                                   "fwd_kernel_ms": min(fw), "fwd_grad_kernel_ms": min(gr),
                                   "ratio": min(gr) / min(fw)}
+    if not a.no_extras and not a.no_batched:
         # batched: one persistent launch vs the plain forward on every
         # (graph, probability vector) pair of the same workload
         nets, pvs = W.config3()

@@ -187,6 +187,7 @@ struct Plan {
 // Every other arc keeps the relative order of kind 0.
 constexpr int kPermKinds = 4;
 constexpr int kDefaultPerm = 3;  // untuned whole sweeps
+constexpr int kGradThreeWaveNodes = 28;  // gradient sweeps of graphs up to this size run 3 waves/SIMD
 
 void assign_bits(int m, const std::vector<int> &rel_bfs, const std::vector<char> &rel, int kind,
                  std::vector<int> &cb_of_arc)
@@ -420,10 +421,18 @@ std::string jit_source(const Plan &P, bool grad)
     for (int b = 0; b < 6; ++b) s += (b ? "," : "") + std::to_string(ck[b]);
     s += "};\n";
     s += "};\n";
-    if (grad)
+    // the gradient sweep of a small graph fits three wavefronts per SIMD
+    // with spills confined to once-per-segment code; larger graphs keep the
+    // compiler's register budget
+    if (grad && P.N <= kGradThreeWaveNodes)
+        s += "extern \"C\" __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))\n"
+             "bat_grad_jit(bat::KParams P) {\n"
+             "  __shared__ bat::LdsTables L; __shared__ bat::LdsGrad LG;\n"
+             "  bat::sweep_kernel<bat::StaticClosure<JitGraph, false>, true>(P, L, &LG);\n}\n";
+    else if (grad)
         s += "extern \"C\" __global__ void __launch_bounds__(256) bat_grad_jit(bat::KParams P) {\n"
              "  __shared__ bat::LdsTables L; __shared__ bat::LdsGrad LG;\n"
-             "  bat::sweep_kernel<bat::StaticClosure<JitGraph>, true>(P, L, &LG);\n}\n";
+             "  bat::sweep_kernel<bat::StaticClosure<JitGraph, false>, true>(P, L, &LG);\n}\n";
     else
         s += "extern \"C\" __global__ void __launch_bounds__(256) bat_fwd_jit(bat::KParams P) {\n"
              "  __shared__ bat::LdsTables L;\n"
