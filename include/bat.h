@@ -209,6 +209,19 @@ typedef struct {
 
 int bat_last_launch(bat_launch_info *info);
 
+/*
+ * The source text of the graph-specialised kernel that the library hands
+ * to hiprtc for this graph: the forward sweep, or the gradient sweep when
+ * grad != 0, with arc-to-counter-bit order `perm` (0..3, as "BAT_PERM").
+ * Diagnostics only; needs no GPU.  The text is what hiprtc compiles: it
+ * declares no headers.  buf (may be NULL) receives at most *len bytes
+ * including the terminating NUL; *len is set to the size needed.
+ * Returns BAT_EINVAL on an invalid graph or perm, BAT_ETOOBIG if buf is
+ * too small (nothing written).
+ */
+int bat_jit_source(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, int32_t s, int32_t t, int32_t grad,
+                   int32_t perm, char *buf, uint64_t *len);
+
 #ifdef __cplusplus
 }
 #endif

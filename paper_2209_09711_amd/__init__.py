@@ -31,7 +31,7 @@ BAT_MAX_PVEC = 1024
 EXPORTED = ("bat_version", "bat_last_error", "bat_reliability", "bat_reliability_grad",
             "bat_reliability_range", "bat_reliability_batched", "bat_reliability_async",
             "bat_reliability_grad_async", "bat_set_option", "bat_get_option", "bat_autotune",
-            "bat_last_launch")
+            "bat_last_launch", "bat_jit_source")
 
 
 class bat_arc(ctypes.Structure):
@@ -75,6 +75,7 @@ def _load():
         "bat_get_option": ([ctypes.c_char_p, P], ctypes.c_int),
         "bat_autotune": ([i32, i32, P, P, i32, i32, P], ctypes.c_int),
         "bat_last_launch": ([P], ctypes.c_int),
+        "bat_jit_source": ([i32, i32, P, i32, i32, i32, i32, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -229,6 +230,16 @@ def bat_autotune(n_nodes: int, arcs, p, s: int, t: int) -> float:
     ns = ctypes.c_double(0.0)
     _check(_lib.bat_autotune(n_nodes, a.shape[0], _ptr(a), _ptr(pv), s, t, ctypes.byref(ns)))
     return ns.value
+
+
+def bat_jit_source(n_nodes: int, arcs, s: int, t: int, grad: bool = False, perm: int = 0) -> str:
+    """The hiprtc source of the graph-specialised kernel (diagnostics)."""
+    a = _arcs(arcs)
+    n = ctypes.c_uint64(0)
+    _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, int(grad), perm, None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, int(grad), perm, buf, ctypes.byref(n)))
+    return buf.value.decode()
 
 
 def bat_last_launch() -> bat_launch_info:

@@ -171,6 +171,7 @@ struct Plan {
     int N = 0, S = 0, T = 0;              // relevant nodes, renumbered
     std::vector<int> ru, rv, rb, rd;      // relaxations (forward order): nodes, counter bit, discovers rv
     std::vector<u32> code, wconst;        // the same for the generic kernel
+    std::vector<u32> prog;                // code/wconst pairs, groups of 4, forward then backward
     std::string structure;                // JIT key (graph structure only)
 };
 
@@ -316,12 +317,35 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
         P.code[k] = (u32)P.ru[k] | ((u32)P.rv[k] << 6) | ((u32)P.rb[k] << 12);
         P.wconst[k] = P.rb[k] < bat::kSliceBits ? bat::slice_pattern(P.rb[k]) : 0u;
     }
+    // the generic kernel's program: (code, pattern) pairs in sweep order,
+    // each direction padded to whole groups of 4 with (0, 0), which relaxes
+    // node 0 against itself with an empty mask (a no-op)
+    {
+        const size_t nr = P.code.size(), ng = (nr + 3) / 4;
+        P.prog.assign(2 * ng * 8 + 8, 0u);  // + the spare group read ahead of the last
+        for (size_t k = 0; k < nr; ++k) {
+            P.prog[2 * k] = P.code[k];
+            P.prog[2 * k + 1] = P.wconst[k];
+            const size_t kb = nr - 1 - k;  // backward sweep position of relaxation k
+            P.prog[ng * 8 + 2 * kb] = P.code[k];
+            P.prog[ng * 8 + 2 * kb + 1] = P.wconst[k];
+        }
+    }
     std::string sdesc = "N" + std::to_string(P.N) + " S" + std::to_string(P.S) + " T" + std::to_string(P.T) +
                         " m" + std::to_string(m) + " :";
     for (size_t k = 0; k < P.ru.size(); ++k)
         sdesc += " " + std::to_string(P.ru[k]) + "," + std::to_string(P.rv[k]) + "," + std::to_string(P.rb[k]) +
                  (P.rd[k] ? "d" : "");
     P.structure = sdesc;
+}
+
+// Relaxation code of each chained counter bit 11 + b (b = 0..5), ~0 where
+// that arc is pruned (no relaxation) or absent.
+void chain_codes(const Plan &P, u32 out[6])
+{
+    for (int b = 0; b < 6; ++b) out[b] = ~0u;
+    for (size_t k = 0; k < P.code.size(); ++k)
+        if (P.rb[k] >= bat::kWordBits && P.rb[k] < bat::kWordBits + 6) out[P.rb[k] - bat::kWordBits] = P.code[k];
 }
 
 // ------------------------------------------------------------ device state
@@ -561,12 +585,12 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     bool use_jit = false;
     if (tc.jit == 1) use_jit = true;
     else if (tc.jit == 2) use_jit = (rq.c_hi - rq.c_lo) >= (1ull << 32) || (P.N > 32 && (rq.c_hi - rq.c_lo) >= (1ull << 22));
-    // warm-started chains need the specialised closure and >= k iteration
-    // bits; k = 3..6 (the gradient sweep keeps at most 4 fast bits: k <= 4)
+    // warm-started chains need >= k iteration bits; k = 3..6 (the gradient
+    // sweep keeps at most 4 fast bits: k <= 4)
     u32 ck = tc.chain < 0 ? 3u : (tc.chain >= 6 ? 6u : (tc.chain >= 3 ? (u32)tc.chain : 0u));
     if (rq.grad && ck > (u32)bat::kGradFastMax) ck = bat::kGradFastMax;
     if (ubits < ck) ck = ubits >= 3 ? 3u : 0u;
-    const bool chain = use_jit && ck > 0 && !P.ru.empty();
+    const bool chain = ck > 0 && !P.ru.empty();
     const u64 bmask = chain ? (1ull << ck) - 1ull : 0ull;
     const u64 g_base = g_first & ~bmask;
     const u64 g_end = g_last | bmask;
@@ -616,6 +640,8 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     K.s = (u32)P.S;
     K.t = (u32)P.T;
     K.n_relax = (u32)P.code.size();
+    K.n_groups = (u32)((P.prog.size() - 8) / 16);
+    chain_codes(P, K.ck_code);
     L.ncol = K.ncol;
 
     // workspace: tables | status | relax | rw | partials | counts | res | count
@@ -627,9 +653,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     const size_t o_map = off;  // row[64] | cb_of_arc[64]
     off = align_up(off + 128, 256);
     const size_t o_rl = off;
-    off = align_up(off + sizeof(u32) * (P.code.size() + 1), 256);
-    const size_t o_rw = off;
-    off = align_up(off + sizeof(u32) * (P.code.size() + 1), 256);
+    off = align_up(off + sizeof(u32) * (P.prog.size() + 1), 256);
     const size_t o_part = off;
     off = align_up(off + sizeof(double) * 2 * K.ncol * K.n_chunks, 256);
     const size_t o_pc = off;
@@ -643,8 +667,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     L.ws = ws;
     K.tables = (const double *)(ws + o_tab);
     K.status = (const int *)(ws + o_st);
-    K.relax = (const u32 *)(ws + o_rl);
-    K.rw = (const u32 *)(ws + o_rw);
+    K.prog = (const u32 *)(ws + o_rl);
     K.part = (double *)(ws + o_part);
     K.pcount = (u64 *)(ws + o_pc);
     L.res = (double *)(ws + o_res);
@@ -660,10 +683,8 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     const bool identity = P.perm == 0 || P.m <= bat::kWordBits;
     const unsigned char *d_row = identity ? nullptr : (const unsigned char *)(ws + o_map);
     L.cb_of_arc = identity ? nullptr : (const unsigned char *)(ws + o_map + 64);
-    if (!P.code.empty()) {
-        HIPCHK(hipMemcpyAsync((void *)K.relax, P.code.data(), sizeof(u32) * P.code.size(), hipMemcpyHostToDevice, stream));
-        HIPCHK(hipMemcpyAsync((void *)K.rw, P.wconst.data(), sizeof(u32) * P.code.size(), hipMemcpyHostToDevice, stream));
-    }
+    if (!P.prog.empty())
+        HIPCHK(hipMemcpyAsync((void *)K.prog, P.prog.data(), sizeof(u32) * P.prog.size(), hipMemcpyHostToDevice, stream));
 
     hipFunction_t jfn = nullptr;
     double jit_ms = 0.0;
@@ -926,6 +947,27 @@ int bat_last_launch(bat_launch_info *info)
     return BAT_OK;
 }
 
+int bat_jit_source(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, int32_t grad, int32_t perm,
+                   char *buf, uint64_t *len)
+{
+    t_err.clear();
+    if (!len) return fail(BAT_EINVAL, "len is NULL");
+    int rc = validate(n, m, arcs, nullptr, s, t);
+    if (rc) return rc;
+    if (perm < 0 || perm >= kPermKinds) return fail(BAT_EINVAL, "perm %d outside [0, %d)", perm, kPermKinds);
+    Plan P;
+    make_plan(n, m, arcs, s, t, P, perm);
+    const std::string src = jit_source(P, grad != 0);
+    const uint64_t need = (uint64_t)src.size() + 1;
+    const uint64_t have = *len;
+    *len = need;
+    if (!buf) return BAT_OK;
+    if (have < need) return fail(BAT_ETOOBIG, "buffer of %llu bytes, need %llu", (unsigned long long)have,
+                                 (unsigned long long)need);
+    memcpy(buf, src.c_str(), need);
+    return BAT_OK;
+}
+
 int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
                  double *best_ns_per_vector)
 {
@@ -1046,17 +1088,19 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
 
     // plans, entries (graph x group of <= 32 p-vectors), longest first
     std::vector<Plan> plans(n_graphs);
-    std::vector<u32> codes, rws;
-    std::vector<u32> relax_off(n_graphs);
+    std::vector<u32> progs;
+    std::vector<u32> prog_off(n_graphs);
     int nmax = 2;
     for (int32_t g = 0; g < n_graphs; ++g) {
         int32_t m = arc_offsets[g + 1] - arc_offsets[g];
         make_plan(n_nodes[g], m, arcs + arc_offsets[g], s[g], t[g], plans[g]);
-        relax_off[g] = (u32)codes.size();
-        codes.insert(codes.end(), plans[g].code.begin(), plans[g].code.end());
-        rws.insert(rws.end(), plans[g].wconst.begin(), plans[g].wconst.end());
+        prog_off[g] = (u32)progs.size();
+        progs.insert(progs.end(), plans[g].prog.begin(), plans[g].prog.end());
         nmax = std::max(nmax, plans[g].N);
     }
+    // chained iteration bits (option BAT_CHAIN_LOG2: -1 = 3, 0 = none, 3..6)
+    const int64_t copt = opts().chain_log2.load();
+    const int bchain = copt < 0 ? 3 : (copt >= 3 ? (int)std::min<int64_t>(copt, 6) : 0);
     std::vector<batk::BatchEntry> ents;
     for (int32_t g = 0; g < n_graphs; ++g) {
         const Plan &P = plans[g];
@@ -1073,7 +1117,11 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
             e.s = (u32)P.S;
             e.t = (u32)P.T;
             e.n_relax = (u32)P.code.size();
-            e.relax_off = relax_off[g];
+            e.prog_off = prog_off[g];
+            e.n_groups = (u32)((P.prog.size() - 8) / 16);
+            // warm-started chains over k <= f iteration bits
+            e.chain = (bchain >= 3 && e.f >= (u32)bchain) ? (u32)bchain : (e.f >= 3 && bchain >= 3 ? e.f : 0u);
+            chain_codes(P, e.ck_code);
             e.graph = (u32)g;
             e.pv_base = (u32)b;
             ents.push_back(e);
@@ -1089,7 +1137,7 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
     for (size_t i = 0; i < ents.size(); ++i) {
         batk::BatchEntry &e = ents[i];
         u64 iters = 1ull << e.ubits;
-        u64 per_item = (u64)batk::kBatchWaves << e.f;
+        u64 per_item = (u64)batk::batch_waves(nmax) << e.f;
         e.item_begin = n_items;
         e.n_items = (iters + per_item - 1) / per_item;
         e.tab_off = tab;
@@ -1111,8 +1159,7 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     const size_t o_ent = take(sizeof(batk::BatchEntry) * ents.size());
     const size_t o_ist = take(sizeof(u64) * item_start.size());
-    const size_t o_code = take(sizeof(u32) * (codes.size() + 1));
-    const size_t o_rw = take(sizeof(u32) * (codes.size() + 1));
+    const size_t o_prog = take(sizeof(u32) * (progs.size() + 1));
     const size_t o_pe = take(sizeof(u32) * pair_entry.size());
     const size_t o_pp = take(sizeof(u32) * pair_pv.size());
     const size_t o_epo = take(sizeof(u64) * entry_p_off.size());
@@ -1130,8 +1177,7 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
     };
     HIPCHK(h2d(o_ent, ents.data(), sizeof(batk::BatchEntry) * ents.size()));
     HIPCHK(h2d(o_ist, item_start.data(), sizeof(u64) * item_start.size()));
-    HIPCHK(h2d(o_code, codes.data(), sizeof(u32) * codes.size()));
-    HIPCHK(h2d(o_rw, rws.data(), sizeof(u32) * rws.size()));
+    HIPCHK(h2d(o_prog, progs.data(), sizeof(u32) * progs.size()));
     HIPCHK(h2d(o_pe, pair_entry.data(), sizeof(u32) * pair_entry.size()));
     HIPCHK(h2d(o_pp, pair_pv.data(), sizeof(u32) * pair_pv.size()));
     HIPCHK(h2d(o_epo, entry_p_off.data(), sizeof(u64) * entry_p_off.size()));
@@ -1153,8 +1199,7 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
     BP.n_entries = (u32)ents.size();
     BP.check_every = opts().check_every.load() >= 2 ? 2u : 1u;
     BP.n_items = n_items;
-    BP.codes = (const u32 *)(ws + o_code);
-    BP.rw = (const u32 *)(ws + o_rw);
+    BP.prog = (const u32 *)(ws + o_prog);
     BP.tables = (const double *)(ws + o_tab);
     BP.part = (double *)(ws + o_part);
     BP.pcount = (u64 *)(ws + o_pc);
@@ -1175,7 +1220,11 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
     I.specialised = 0;
     I.chunk_log2 = batk::kBatchSegLog;
     I.n_chunks = (int32_t)std::min<u64>(n_items, 0x7fffffff);
-    I.relaxations = (int32_t)codes.size();
+    {
+        size_t nrel = 0;
+        for (const Plan &pl : plans) nrel += pl.code.size();
+        I.relaxations = (int32_t)nrel;
+    }
     t_state.have_launch = true;
     return BAT_OK;
 }

@@ -214,9 +214,11 @@ k_batched_tables(const batk::BatchEntry *__restrict__ entries, const u32 *__rest
 // in a fixed order into the item's own partial slot }.  Items are queued
 // longest graph first.  Every wavefront leaves when the queue is empty.
 template <int NMAX>
-__global__ void __launch_bounds__(batk::kBatchThreads) k_batched_dyn(batk::BatchParams B)
+__global__ void __launch_bounds__(batk::batch_waves(NMAX) * bat::kWave) k_batched_dyn(batk::BatchParams B)
 {
     using namespace batk;
+    constexpr int kBatchWaves = batch_waves(NMAX);
+    constexpr int kBatchThreads = kBatchWaves * bat::kWave;
     __shared__ double tb[kBatchMaxP][256];
     __shared__ double a4[kBatchMaxP][4];
     __shared__ double qlo[kBatchMaxP][1 << kBatchSegLog];
@@ -238,9 +240,12 @@ __global__ void __launch_bounds__(batk::kBatchThreads) k_batched_dyn(batk::Batch
             s_entry = lo;
         }
         __syncthreads();
-        const u64 item = s_item;
+        // uniform: the entry (and the relaxation program it points to) is
+        // then read with scalar loads
+        const u64 item = ((u64)__builtin_amdgcn_readfirstlane((u32)(s_item >> 32)) << 32) |
+                         __builtin_amdgcn_readfirstlane((u32)s_item);
         if (item >= B.n_items) break;
-        const BatchEntry E = B.entries[s_entry];
+        const BatchEntry E = B.entries[__builtin_amdgcn_readfirstlane(s_entry)];
         const u32 P = E.P, f = E.f;
         const double *T = B.tables + E.tab_off;
         for (u32 i = tid; i < P * 256u; i += kBatchThreads)
@@ -265,17 +270,19 @@ __global__ void __launch_bounds__(batk::kBatchThreads) k_batched_dyn(batk::Batch
             K.s = E.s;
             K.t = E.t;
             K.n_relax = E.n_relax;
-            K.relax = B.codes + E.relax_off;
-            K.rw = B.rw + E.relax_off;
+            K.n_groups = E.n_groups;
+            K.prog = B.prog + E.prog_off;
+#pragma unroll
+            for (int b = 0; b < 6; ++b) K.ck_code[b] = E.ck_code[b];
             K.check_every = B.check_every;
             bat::DynClosure<NMAX> cl;
             cl.init(lane, K);
             const u64 chi = E.m >= 63 ? ~0ull : (1ull << E.m);
-            for (u64 g = g0; g <= g1; ++g) {
-                u32 V = cl.verdict(g, K);
+            // one verdict word of iteration g into all P accumulators
+            auto add = [&](u64 g, u32 V) {
                 if (g == iters - 1) V &= bat::edge_mask(0ull, chi, g, lane);
                 cnt += __popc(V);
-                if (__ballot(V != 0u) == 0ull) continue;
+                if (__ballot(V != 0u) == 0ull) return;
                 const u32 b0 = V & 255u, b1 = (V >> 8) & 255u, b2 = (V >> 16) & 255u, b3 = V >> 24;
                 const u32 glo = (u32)(g & ((1ull << f) - 1ull));
                 // re-read the per-vector byte factors every iteration (held in
@@ -294,7 +301,9 @@ __global__ void __launch_bounds__(batk::kBatchThreads) k_batched_dyn(batk::Batch
                         tot[q] = __builtin_fma(qlo[q][glo], F, tot[q]);
                     }
                 }
-            }
+            };
+            // chained blocks of 2^k iterations (f >= k: inside this segment)
+            cl.sweep_range(g0, g1, E.chain, K, add, [](u64, u64) {});
         }
         // Q_hi of this segment and Q_L of the lane, then across the wavefront
 #pragma unroll
@@ -406,10 +415,10 @@ hipError_t batched_tables(hipStream_t st, const BatchEntry *entries, const u32 *
 
 hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, const BatchParams &B)
 {
-    const dim3 g(blocks), b(kBatchThreads);
-    if (nmax <= 16) hipLaunchKernelGGL(k_batched_dyn<16>, g, b, 0, st, B);
-    else if (nmax <= 32) hipLaunchKernelGGL(k_batched_dyn<32>, g, b, 0, st, B);
-    else hipLaunchKernelGGL(k_batched_dyn<64>, g, b, 0, st, B);
+    const dim3 g(blocks);
+    if (nmax <= 16) hipLaunchKernelGGL(k_batched_dyn<16>, g, dim3(batch_waves(16) * bat::kWave), 0, st, B);
+    else if (nmax <= 32) hipLaunchKernelGGL(k_batched_dyn<32>, g, dim3(batch_waves(32) * bat::kWave), 0, st, B);
+    else hipLaunchKernelGGL(k_batched_dyn<64>, g, dim3(batch_waves(64) * bat::kWave), 0, st, B);
     return hipGetLastError();
 }
 

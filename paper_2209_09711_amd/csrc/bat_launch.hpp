@@ -8,18 +8,25 @@
 namespace batk {
 
 // ---- batched form: many graphs x many probability vectors in one launch.
-constexpr int kBatchWaves = 8;                  // wavefronts per block (one block per CU: LDS-bound)
-constexpr int kBatchThreads = kBatchWaves * bat::kWave;
+// wavefronts per block (one block per CU: LDS-bound): 3 per SIMD while the
+// reach words, which persist across a chained block, fit beside the 32
+// accumulators in 168 VGPRs, else 2
+constexpr int batch_waves(int nmax) { return nmax <= 16 ? 12 : 8; }
+constexpr int kBatchWavesMax = 12;
 constexpr int kBatchMaxP = 32;                  // probability vectors per entry
 constexpr int kBatchSegLog = 6;                 // iterations per wavefront work unit: 2^f
 
 // One (graph, group of <= 32 probability vectors).  Its work is split into
-// items of kBatchWaves * 2^f iterations; items of all entries form one queue.
+// items of batch_waves(nmax) * 2^f iterations; items of all entries form one
+// queue.
 struct BatchEntry {
     bat::u32 m, ubits, f, P;
     bat::u32 n_nodes, s, t, n_relax;
-    bat::u32 relax_off;   // into the concatenated relaxation lists
-    bat::u32 graph, pv_base, pad;
+    bat::u32 prog_off;    // into the concatenated relaxation programs (u32s)
+    bat::u32 n_groups;    // relaxation groups of 4 per sweep direction
+    bat::u32 graph, pv_base;
+    bat::u32 chain;       // k: warm-started chains over the k lowest iteration bits (0: none)
+    bat::u32 ck_code[6];  // relaxation code of counter bit 11 + b (~0: pruned)
     bat::u64 item_begin, n_items;
     bat::u64 tab_off;     // doubles: P consecutive forward table blocks
 };
@@ -29,7 +36,7 @@ struct BatchParams {
     const bat::u64 *item_start;   // [n_entries + 1], ascending
     bat::u32 n_entries, check_every;
     bat::u64 n_items;
-    const bat::u32 *codes, *rw;
+    const bat::u32 *prog;         // concatenated relaxation programs (bat::KParams::prog)
     const double *tables;
     double *part;                 // [n_items][kBatchMaxP][2]
     bat::u64 *pcount;             // [n_items]
