@@ -214,6 +214,11 @@ def main():
         nets, pvs = W.config3()
         graphs = [(g.n, g.arc_array(), g.s, g.t) for g in nets]
         B.bat_reliability_batched(graphs, pvs)
+        # autotune (one-time, reported separately): chain length and
+        # segment size of the batched launch on this batch
+        t0 = time.perf_counter()
+        B.bat_autotune_batched(graphs, pvs)
+        btune_s = time.perf_counter() - t0
         t0 = time.perf_counter()
         Rb, cb = B.bat_reliability_batched(graphs, pvs)
         bw = time.perf_counter() - t0
@@ -232,7 +237,7 @@ def main():
         out["batched_vs_plain"] = {
             "workload": f"{len(nets)} random graphs, n 8-16, m 16-28 (seed 220909711/3), "
                         f"{pvs[0].shape[0]} p-vectors each, {vec} state vectors x {pvs[0].shape[0]}",
-            "batched_wall_ms": bw * 1e3, "batched_kernel_ms": bk,
+            "batched_wall_ms": bw * 1e3, "batched_kernel_ms": bk, "batched_autotune_s": btune_s,
             "plain_wall_ms": pw * 1e3, "plain_kernel_ms_sum": pk,
             "speedup_wall": pw / bw, "max_rel_diff": worst}
 

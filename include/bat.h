@@ -120,6 +120,20 @@ int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes, const int3
                             int32_t n_pvec, const double *p, double *R_out, uint64_t *counts_out);
 
 /*
+ * Autotuner for the batched launch: runs this batch (same arguments as
+ * bat_reliability_batched, results discarded) with each candidate number
+ * of chained iteration bits (0, 3..6) and per-wavefront segment size
+ * (2^4..2^6 iterations), and caches the fastest under the batch's
+ * structure (graphs, terminals, n_pvec; not p).  Later batched calls with
+ * that structure use it while "BAT_AUTOTUNE" is 1 and "BAT_CHAIN_LOG2" is
+ * -1.  *best_kernel_ms (may be NULL) receives the best kernel time.
+ * Results never depend on the choice beyond floating-point rounding.
+ */
+int bat_autotune_batched(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_offsets,
+                         const bat_arc *arcs, const int32_t *s, const int32_t *t, int32_t n_pvec,
+                         const double *p, double *best_kernel_ms);
+
+/*
  * Stream-ordered forms for callers that keep p and the results in device
  * memory (e.g. PyTorch tensors).  arcs, n_nodes, s, t are host values; p_dev
  * (n_arcs doubles), R_dev (1 double), count_dev (1 uint64) and, for the

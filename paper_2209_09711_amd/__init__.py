@@ -31,7 +31,7 @@ BAT_MAX_PVEC = 1024
 EXPORTED = ("bat_version", "bat_last_error", "bat_reliability", "bat_reliability_grad",
             "bat_reliability_range", "bat_reliability_batched", "bat_reliability_async",
             "bat_reliability_grad_async", "bat_set_option", "bat_get_option", "bat_autotune",
-            "bat_last_launch", "bat_jit_source")
+            "bat_last_launch", "bat_jit_source", "bat_autotune_batched")
 
 
 class bat_arc(ctypes.Structure):
@@ -76,6 +76,7 @@ def _load():
         "bat_autotune": ([i32, i32, P, P, i32, i32, P], ctypes.c_int),
         "bat_last_launch": ([P], ctypes.c_int),
         "bat_jit_source": ([i32, i32, P, i32, i32, i32, i32, P, P], ctypes.c_int),
+        "bat_autotune_batched": ([i32, P, P, P, P, P, i32, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -185,9 +186,7 @@ def bat_reliability_range(n_nodes: int, arcs, p, s: int, t: int, c_lo: int, c_hi
     return RangeResult(hi.value, lo.value, cnt.value, None if T1 is None else T1[:m], None if T0 is None else T0[:m])
 
 
-def bat_reliability_batched(graphs: Sequence[Tuple[int, object, int, int]], p_blocks: Sequence[np.ndarray]):
-    """graphs: [(n_nodes, arcs, s, t)], p_blocks[g]: (n_pvec, m_g) array.
-    Returns (R[n_graphs, n_pvec], counts[n_graphs])."""
+def _batch_args(graphs, p_blocks):
     G = len(graphs)
     if G == 0:
         raise ValueError("no graphs")
@@ -206,11 +205,28 @@ def bat_reliability_batched(graphs: Sequence[Tuple[int, object, int, int]], p_bl
             raise ValueError(f"p block {g} has shape {pb.shape}, want {(n_pvec, arcs_l[g].shape[0])}")
         blocks.append(pb.reshape(-1))
     p = np.ascontiguousarray(np.concatenate(blocks) if blocks else np.zeros(1))
+    return G, nn, off, arcs, ss, tt, n_pvec, p
+
+
+def bat_reliability_batched(graphs: Sequence[Tuple[int, object, int, int]], p_blocks: Sequence[np.ndarray]):
+    """graphs: [(n_nodes, arcs, s, t)], p_blocks[g]: (n_pvec, m_g) array.
+    Returns (R[n_graphs, n_pvec], counts[n_graphs])."""
+    G, nn, off, arcs, ss, tt, n_pvec, p = _batch_args(graphs, p_blocks)
     R = np.zeros(G * n_pvec)
     cnt = np.zeros(G, dtype=np.uint64)
     _check(_lib.bat_reliability_batched(G, _ptr(nn), _ptr(off), _ptr(arcs), _ptr(ss), _ptr(tt), n_pvec, _ptr(p),
                                         _ptr(R), _ptr(cnt)))
     return R.reshape(G, n_pvec), cnt
+
+
+def bat_autotune_batched(graphs: Sequence[Tuple[int, object, int, int]], p_blocks: Sequence[np.ndarray]) -> float:
+    """Tune the batched launch for this batch structure; returns the best
+    kernel time in ms."""
+    G, nn, off, arcs, ss, tt, n_pvec, p = _batch_args(graphs, p_blocks)
+    ms = ctypes.c_double(0.0)
+    _check(_lib.bat_autotune_batched(G, _ptr(nn), _ptr(off), _ptr(arcs), _ptr(ss), _ptr(tt), n_pvec, _ptr(p),
+                                     ctypes.byref(ms)))
+    return ms.value
 
 
 def bat_set_option(key: str, value: int):

@@ -1059,9 +1059,36 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
 
 }  // extern "C"
 
-extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_offsets,
-                                       const bat_arc *arcs, const int32_t *s, const int32_t *t, int32_t n_pvec,
-                                       const double *p, double *R_out, uint64_t *counts_out)
+// Tuned knobs of the batched launch: chained iteration bits and the
+// per-wavefront segment size, cached under the batch's structure.
+struct BatchTune {
+    int chain = -1;  // -1: option BAT_CHAIN_LOG2 (-1 = 3)
+    int seg = -1;    // -1: batk::kBatchSegLog
+};
+std::mutex g_btune_mu;
+std::map<std::string, BatchTune> g_btune;
+
+// The batch's structure (graphs, terminals, p-vector count) as a key.
+std::string batch_key(int device, int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_offsets,
+                      const bat_arc *arcs, const int32_t *s, const int32_t *t, int32_t n_pvec)
+{
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the structure
+    auto mix = [&](const void *d, size_t n) {
+        const unsigned char *c = (const unsigned char *)d;
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    };
+    mix(n_nodes, sizeof(int32_t) * n_graphs);
+    mix(arc_offsets, sizeof(int32_t) * (n_graphs + 1));
+    mix(arcs, sizeof(bat_arc) * arc_offsets[n_graphs]);
+    mix(s, sizeof(int32_t) * n_graphs);
+    mix(t, sizeof(int32_t) * n_graphs);
+    return std::to_string(device) + " batch " + std::to_string(n_graphs) + " " + std::to_string(n_pvec) + " " +
+           std::to_string(h);
+}
+
+int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_offsets, const bat_arc *arcs,
+                 const int32_t *s, const int32_t *t, int32_t n_pvec, const double *p, double *R_out,
+                 uint64_t *counts_out, const BatchTune *force)
 {
     t_err.clear();
     if (n_graphs <= 0) return fail(BAT_EINVAL, "n_graphs must be >= 1");
@@ -1098,9 +1125,19 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
         progs.insert(progs.end(), plans[g].prog.begin(), plans[g].prog.end());
         nmax = std::max(nmax, plans[g].N);
     }
-    // chained iteration bits (option BAT_CHAIN_LOG2: -1 = 3, 0 = none, 3..6)
-    const int64_t copt = opts().chain_log2.load();
-    const int bchain = copt < 0 ? 3 : (copt >= 3 ? (int)std::min<int64_t>(copt, 6) : 0);
+    // knobs: forced (autotuner), else the tuned choice, else the options
+    BatchTune bt;
+    if (force) {
+        bt = *force;
+    } else if (opts().autotune.load()) {
+        std::lock_guard<std::mutex> lk(g_btune_mu);
+        auto it = g_btune.find(batch_key(D.id, n_graphs, n_nodes, arc_offsets, arcs, s, t, n_pvec));
+        if (it != g_btune.end()) bt = it->second;
+    }
+    if (!force && opts().chain_log2.load() >= 0) bt.chain = (int)opts().chain_log2.load();
+    // chained iteration bits (-1 = 3, 0 = none, 3..6)
+    const int bchain = bt.chain < 0 ? 3 : (bt.chain >= 3 ? std::min(bt.chain, 6) : 0);
+    const u32 bseg = bt.seg > 0 ? (u32)std::min(bt.seg, batk::kBatchSegLog) : (u32)batk::kBatchSegLog;
     std::vector<batk::BatchEntry> ents;
     for (int32_t g = 0; g < n_graphs; ++g) {
         const Plan &P = plans[g];
@@ -1111,7 +1148,7 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
             memset(&e, 0, sizeof e);
             e.m = m;
             e.ubits = ubits;
-            e.f = std::min<u32>(ubits, batk::kBatchSegLog);
+            e.f = std::min<u32>(ubits, bseg);
             e.P = (u32)std::min<int32_t>(batk::kBatchMaxP, n_pvec - b);
             e.n_nodes = (u32)P.N;
             e.s = (u32)P.S;
@@ -1218,7 +1255,7 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
     memset(&I, 0, sizeof I);
     I.vectors = vectors;
     I.specialised = 0;
-    I.chunk_log2 = batk::kBatchSegLog;
+    I.chunk_log2 = (int32_t)bseg;
     I.n_chunks = (int32_t)std::min<u64>(n_items, 0x7fffffff);
     {
         size_t nrel = 0;
@@ -1226,5 +1263,59 @@ extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes,
         I.relaxations = (int32_t)nrel;
     }
     t_state.have_launch = true;
+    return BAT_OK;
+}
+
+extern "C" int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_offsets,
+                                       const bat_arc *arcs, const int32_t *s, const int32_t *t, int32_t n_pvec,
+                                       const double *p, double *R_out, uint64_t *counts_out)
+{
+    return batched_impl(n_graphs, n_nodes, arc_offsets, arcs, s, t, n_pvec, p, R_out, counts_out, nullptr);
+}
+
+extern "C" int bat_autotune_batched(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_offsets,
+                                    const bat_arc *arcs, const int32_t *s, const int32_t *t, int32_t n_pvec,
+                                    const double *p, double *best_kernel_ms)
+{
+    t_err.clear();
+    if (n_graphs <= 0 || !n_nodes || !arc_offsets || !arcs || !s || !t)
+        return fail(BAT_EINVAL, "invalid batch description");
+    if (n_pvec < 1 || n_pvec > BAT_MAX_PVEC) return fail(BAT_EINVAL, "n_pvec %d outside [1, %d]", n_pvec, BAT_MAX_PVEC);
+    DeviceInfo D;
+    int rc = current_device(D);
+    if (rc) return rc;
+    std::vector<double> R((size_t)n_graphs * n_pvec);
+    std::vector<uint64_t> cnt((size_t)n_graphs);
+    const char *vb = getenv("BAT_AUTOTUNE_VERBOSE");
+    const bool verbose = vb && *vb && *vb != '0';
+    // the whole batch, each candidate once untimed and then the best of two
+    // (a batch is one launch: sampling it would change its load balance)
+    double best = 1e300;
+    BatchTune bb;
+    for (int seg : {6, 5, 4})
+        for (int chain : {0, 3, 4, 5, 6}) {
+            if (chain > seg) continue;
+            const BatchTune c{chain, seg};
+            double ms = 1e300;
+            for (int rep = 0; rep < 3; ++rep) {
+                rc = batched_impl(n_graphs, n_nodes, arc_offsets, arcs, s, t, n_pvec, p, R.data(), cnt.data(), &c);
+                if (rc) return rc;
+                bat_launch_info li;
+                rc = bat_last_launch(&li);
+                if (rc) return rc;
+                if (rep > 0) ms = std::min(ms, li.kernel_ms);
+            }
+            if (verbose) fprintf(stderr, "bat_autotune_batched: seg_log2=%d chain=%d -> %.3f ms\n", seg, chain, ms);
+            if (ms < best) {
+                best = ms;
+                bb = c;
+            }
+        }
+    {
+        std::lock_guard<std::mutex> lk(g_btune_mu);
+        g_btune[batch_key(D.id, n_graphs, n_nodes, arc_offsets, arcs, s, t, n_pvec)] = bb;
+    }
+    if (best_kernel_ms) *best_kernel_ms = best;
+    t_err.clear();
     return BAT_OK;
 }

@@ -511,6 +511,36 @@ def test_batched_vs_plain_and_oracle(n_pvec):
             assert cnt[g] == o.count and rel_ok(R[g, 0], o.sum)
 
 
+@pytest.mark.parametrize("k", [0, 3, 4, 5, 6])
+def test_batched_chain_lengths(k):
+    """Warm-started chains in the batched launch: counts exact, R equal to the
+    unchained launch to rounding, on graphs large enough to chain."""
+    B = _B()
+    graphs, pblocks = _batch_inputs(700 + k, 20, 5)
+    with options(BAT_CHAIN_LOG2=0):
+        R0, c0 = B.bat_reliability_batched(graphs, pblocks)
+    with options(BAT_CHAIN_LOG2=k):
+        say("batched chain", k, len(graphs))
+        R, c = B.bat_reliability_batched(graphs, pblocks)
+    assert np.array_equal(c, c0)
+    assert np.allclose(R, R0, rtol=1e-12, atol=0)
+    g = max(range(len(graphs)), key=lambda i: len(graphs[i][1]))
+    n, arcs, s_, t_ = graphs[g]
+    Rd, cd = frontier_dp.reliability(n, arcs, pblocks[g][0], s_, t_)
+    assert c[g] == cd and rel_ok(R[g, 0], Rd)
+
+
+def test_batched_autotune_keeps_results():
+    B = _B()
+    graphs, pblocks = _batch_inputs(777, 12, 9)
+    R0, c0 = B.bat_reliability_batched(graphs, pblocks)
+    ms = B.bat_autotune_batched(graphs, pblocks)
+    say("batched autotune ms", ms)
+    assert 0.0 < ms < 1e4
+    R1, c1 = B.bat_reliability_batched(graphs, pblocks)
+    assert np.array_equal(c1, c0) and np.allclose(R1, R0, rtol=1e-12, atol=0)
+
+
 def test_batched_config3_workload():
     """256 graphs x 32 probability vectors in one persistent launch."""
     B = _B()
