@@ -37,7 +37,7 @@ PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 1.26e15 bit-ops/s
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain 1 GiB copy
 # (profiles/bat_fwd_jit_grid5x5_m40.md), keyed by the hash of the kernel and
 # host sources they were measured on; any other source reports null.
-MEASURED_TRAFFIC = {"4f3d07213b5b": (108.1 * 2.0 + 3072.0 * 1.0) * 1024}
+MEASURED_TRAFFIC = {"9b8eb4ba9f83": (149.44 * 2.0 + 3072.0 * 1.0) * 1024}
 
 
 def source_hash() -> str:
@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the fwd+grad / batched comparisons")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only tune and time the batched launch on its workload (for profiling runs)")
     ap.add_argument("--cpu-sample-log2", type=int, default=30,
                     help="log2 of the state vectors in the oracle's timed sample")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
@@ -100,10 +102,35 @@ def cpu_baseline(net, sample_log2: int):
     }
 
 
+def batched_only():
+    """The batched workload alone: tune, then time three launches."""
+    import numpy as np
+    import torch
+
+    import bat_workloads as W
+    import paper_2209_09711_amd as B
+
+    torch.cuda.set_device(0)
+    nets, pvs = W.config3()
+    graphs = [(g.n, g.arc_array(), g.s, g.t) for g in nets]
+    B.bat_autotune_batched(graphs, pvs)
+    ks = []
+    for _ in range(3):
+        B.bat_reliability_batched(graphs, pvs)
+        ks.append(B.bat_last_launch().kernel_ms)
+    vec = sum(1 << g.m for g in nets)
+    print(json.dumps({"workload": f"{len(nets)} random graphs x {pvs[0].shape[0]} p-vectors (seed 220909711/3)",
+                      "state_vectors": vec, "batched_kernel_ms": float(np.min(ks)),
+                      "batched_kernel_ms_all": ks}), flush=True)
+
+
 def main():
     a = parse()
     if a.copy_ref_gib > 0:
         copy_reference(a.copy_ref_gib)
+        return
+    if a.batched_only:
+        batched_only()
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the enumeration would shard "
