@@ -64,6 +64,12 @@ def _load():
             lib.orc_pr.restype = ctypes.c_double
             lib.orc_range.argtypes = [i32, i32, P, P, i32, i32, i32, u64, u64, P, P, P, P, P, P]
             lib.orc_range.restype = ctypes.c_int
+            lib.orc_range_order.argtypes = [i32, i32, P, P, i32, i32, i32, i32, u64, u64, P, P, P, P, P, P]
+            lib.orc_range_order.restype = ctypes.c_int
+            lib.orc_dec_inv_fwd.argtypes = [i32, u64, P]
+            lib.orc_dec_inv_fwd.restype = None
+            lib.orc_bat_next_fwd.argtypes = [i32, P]
+            lib.orc_bat_next_fwd.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -119,12 +125,21 @@ def dec(x) -> int:
     return int(_load().orc_dec(len(xa), _ptr(xa)))
 
 
-def bat_sequence(m: int):
-    """All 2^m vectors in the order the BAT of Section 3.1 generates them."""
+def dec_inv_fwd(m: int, c: int) -> tuple:
+    """Eq. 5 (forward BAT): the 0-based c-th vector, x_1 least significant."""
+    x = np.zeros(max(m, 1), dtype=np.uint8)
+    _load().orc_dec_inv_fwd(m, c, _ptr(x))
+    return tuple(int(v) for v in x[:m])
+
+
+def bat_sequence(m: int, forward: bool = False):
+    """All 2^m vectors in the order the BAT of Section 3.1 generates them
+    (forward=True: the forward BAT of Section 4.2, updating from x_1)."""
     lib = _load()
+    step = lib.orc_bat_next_fwd if forward else lib.orc_bat_next
     x = np.zeros(max(m, 1), dtype=np.uint8)
     out = [tuple(int(v) for v in x[:m])]
-    while lib.orc_bat_next(m, _ptr(x)):
+    while step(m, _ptr(x)):
         out.append(tuple(int(v) for v in x[:m]))
     return out
 
@@ -150,8 +165,9 @@ def pr(p, x) -> float:
     return float(_load().orc_pr(len(pv), _ptr(pv), _ptr(xa)))
 
 
-def reliability_range(n, arcs, p, s, t, c_lo, c_hi, grad=False, directed=False) -> RangeResult:
-    """BAT over backward-order indices [c_lo, c_hi)."""
+def reliability_range(n, arcs, p, s, t, c_lo, c_hi, grad=False, directed=False, forward=False) -> RangeResult:
+    """BAT over backward-order indices [c_lo, c_hi) (forward=True: forward
+    BAT indices, Eq. 4-5)."""
     a = _arcs(arcs)
     m = a.shape[0]
     pv = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
@@ -163,8 +179,9 @@ def reliability_range(n, arcs, p, s, t, c_lo, c_hi, grad=False, directed=False) 
     stats = np.zeros(2, dtype=np.int64)
     T1 = np.zeros(2 * max(m, 1)) if grad else None
     T0 = np.zeros(2 * max(m, 1)) if grad else None
-    rc = _load().orc_range(n, m, _ptr(a), _ptr(pv), s, t, int(directed), int(c_lo), int(c_hi),
-                           _ptr(sum2), ctypes.byref(cnt), _ptr(usum2), _ptr(T1), _ptr(T0), _ptr(stats))
+    rc = _load().orc_range_order(n, m, _ptr(a), _ptr(pv), s, t, int(directed), int(forward), int(c_lo),
+                                 int(c_hi), _ptr(sum2), ctypes.byref(cnt), _ptr(usum2), _ptr(T1), _ptr(T0),
+                                 _ptr(stats))
     if rc != ORC_OK:
         raise OracleError(rc)
     t1 = t0 = None

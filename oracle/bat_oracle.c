@@ -82,6 +82,29 @@ uint64_t orc_dec(int32_t m, const uint8_t *x)
     return c;
 }
 
+/* Forward BAT (Section 4.2, Eq. 4-5 with the worked examples there:
+ * X_3 = (0,1,0,0,0,0) and X_31 = (0,1,1,1,1,0) when X_1 = 0): coordinate
+ * x_1 is the least significant, x_k = bit (k - 1) of the 0-based index. */
+void orc_dec_inv_fwd(int32_t m, uint64_t c, uint8_t *x)
+{
+    for (int32_t k = 1; k <= m; ++k) x[k - 1] = (uint8_t)((c >> (k - 1)) & 1u);
+}
+
+/* The forward update: Rule 1 applied from the first coordinate, i.e. the
+ * first zero-valued coordinate becomes one and every coordinate before it
+ * becomes zero.  Returns 0 when no zero coordinate is left. */
+int orc_bat_next_fwd(int32_t m, uint8_t *x)
+{
+    for (int32_t k = 1; k <= m; ++k) {
+        if (x[k - 1] == 0) {
+            x[k - 1] = 1;
+            return 1;
+        }
+        x[k - 1] = 0;
+    }
+    return 0;
+}
+
 /* One BAT update (Section 3.1, STEPs B1-B3): Rule 1 turns the last
  * zero-valued coordinate into one and every coordinate after it into zero.
  * Returns 1 if X was updated, 0 if no zero coordinate exists (Rule 2: all
@@ -248,9 +271,23 @@ static void orc_neumaier(double *s, double *c, double x)
  *                  of prod_{j != i} q_j over connected X with x_i = 1 / 0
  *   stats[2]     : total PLSA layers and arc inspections over the range
  */
+int orc_range_order(int32_t n, int32_t m, const int32_t *uv, const double *p, int32_t s, int32_t t,
+                    int32_t directed, int32_t forward, uint64_t c_lo, uint64_t c_hi, double *sum2,
+                    uint64_t *count, double *usum2, double *T1, double *T0, int64_t *stats);
+
 int orc_range(int32_t n, int32_t m, const int32_t *uv, const double *p, int32_t s, int32_t t,
               int32_t directed, uint64_t c_lo, uint64_t c_hi, double *sum2, uint64_t *count,
               double *usum2, double *T1, double *T0, int64_t *stats)
+{
+    return orc_range_order(n, m, uv, p, s, t, directed, 0, c_lo, c_hi, sum2, count, usum2, T1, T0, stats);
+}
+
+/* orc_range with a choice of index order: forward = 0 is the backward BAT
+ * of Section 3.1 (Eq. 2-3), forward = 1 the forward BAT of Section 4.2
+ * (Eq. 4-5). */
+int orc_range_order(int32_t n, int32_t m, const int32_t *uv, const double *p, int32_t s, int32_t t,
+                    int32_t directed, int32_t forward, uint64_t c_lo, uint64_t c_hi, double *sum2,
+                    uint64_t *count, double *usum2, double *T1, double *T0, int64_t *stats)
 {
     int rc = orc_validate(n, m, uv, p, s, t);
     if (rc != ORC_OK) return rc;
@@ -280,7 +317,10 @@ int orc_range(int32_t n, int32_t m, const int32_t *uv, const double *p, int32_t 
         for (int32_t i = 0; i < 2 * m; ++i) T1[i] = T0[i] = 0.0;
 
     if (c_lo < c_hi) {
-        orc_dec_inv(m, c_lo, x); /* the first vector of the range, Eq. 3 */
+        if (forward)
+            orc_dec_inv_fwd(m, c_lo, x); /* the first vector of the range, Eq. 5 */
+        else
+            orc_dec_inv(m, c_lo, x); /* the first vector of the range, Eq. 3 */
         for (uint64_t c = c_lo;;) {
             int32_t L = 0;
             int64_t I = 0;
@@ -307,7 +347,10 @@ int orc_range(int32_t n, int32_t m, const int32_t *uv, const double *p, int32_t 
                 orc_neumaier(&u_sum, &u_cmp, orc_pr(m, p, x));
             }
             if (++c == c_hi) break;
-            orc_bat_next(m, x); /* Rule 1 */
+            if (forward)
+                orc_bat_next_fwd(m, x);
+            else
+                orc_bat_next(m, x); /* Rule 1 */
         }
     }
     sum2[0] = s_sum;

@@ -59,6 +59,39 @@ def test_dec_examples_section_4_2():
     assert oracle.dec_inv(6, 30) == (0, 1, 1, 1, 1, 0)
 
 
+def test_forward_bat_section_4_2():
+    """Forward BAT (updates from x_1): the worked examples of Section 4.2
+    (X_3 = (0,1,0,0,0,0), X_31 = (0,1,1,1,1,0) with X_1 = 0), the update
+    rule agreeing with the decoding, and the forward order of X being the
+    backward order of the reversed coordinate list."""
+    assert oracle.dec_inv_fwd(6, 3 - 1) == (0, 1, 0, 0, 0, 0)
+    assert oracle.dec_inv_fwd(6, 31 - 1) == (0, 1, 1, 1, 1, 0)
+    seq = oracle.bat_sequence(6, forward=True)
+    assert len(seq) == 64 and len(set(seq)) == 64
+    assert seq == [oracle.dec_inv_fwd(6, c) for c in range(64)]
+    back = oracle.bat_sequence(6)
+    assert seq == [tuple(reversed(x)) for x in back]
+    # the first forward step sets x_1; the last vector is all ones
+    assert seq[1] == (1, 0, 0, 0, 0, 0) and seq[-1] == (1,) * 6
+
+
+def test_forward_ranges_match_reversed_backward_ranges():
+    net = W.random_connected(9, 14, seed=404, p_lo=0.2, p_hi=0.95)
+    m = net.m
+    full_f = oracle.reliability_range(net.n, net.arcs, net.p, net.s, net.t, 0, 1 << m, forward=True)
+    full_b = oracle.reliability(net.n, net.arcs, net.p, net.s, net.t)
+    assert full_f.count == full_b.count and abs(full_f.sum - full_b.sum) <= 1e-14
+    rev = list(reversed(net.arcs))
+    prev = np.ascontiguousarray(net.p[::-1])
+    for lo, hi in [(0, 1000), (777, 5432), (1 << 13, (1 << 14) - 3)]:
+        f = oracle.reliability_range(net.n, net.arcs, net.p, net.s, net.t, lo, hi, forward=True, grad=True)
+        b = oracle.reliability_range(net.n, rev, prev, net.s, net.t, lo, hi, grad=True)
+        # same terms; only the product order inside each Pr(X) is reversed
+        assert f.count == b.count and abs(f.sum - b.sum) <= 1e-15 * f.sum
+        assert np.allclose(f.T1, b.T1[::-1], rtol=1e-14, atol=0)
+        assert np.allclose(f.T0, b.T0[::-1], rtol=1e-14, atol=0)
+
+
 def test_equal_divisions_section_4_3_4_4():
     # chi = 4, m = 6: mu = 16; the divisions start at X_1, X_17, X_33, X_49
     starts = [pbat.division_bounds(6, 4, i)[0] + 1 for i in range(1, 5)]
