@@ -101,6 +101,40 @@ int bat_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, 
                           double *T1_out, double *T0_out);
 
 /*
+ * Variants (flags, OR-ed):
+ *   BAT_DIRECTED       arcs are directed, u -> v: f(X) = 1 iff G(X) has a
+ *                      directed s -> t path (the "directed path" wording of
+ *                      the layered search, Section 3.2).  The paper's own
+ *                      results are for the undirected reading.
+ *   BAT_FORWARD_ORDER  range indices follow the forward BAT (Section 4.2,
+ *                      Eq. 4-5): x_1 is the least significant bit of the
+ *                      0-based index, arc i is bit i.  Without it, indices
+ *                      follow the backward BAT of Section 3.1 (Eq. 2-3).
+ *                      A whole sweep does not depend on the order.
+ * Unknown flag bits return BAT_EINVAL.
+ */
+#define BAT_DIRECTED 1u
+#define BAT_FORWARD_ORDER 2u
+
+/*
+ * bat_reliability / bat_reliability_grad with flags.  dRdp_out, T1_out and
+ * T0_out (n_arcs doubles each) are each nullable; the gradient sweep runs
+ * when any of them is set.  Same errors as above.
+ */
+int bat_reliability_ex(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const double *p,
+                       int32_t s, int32_t t, uint32_t flags, double *R_out, uint64_t *count_out,
+                       double *dRdp_out, double *T1_out, double *T0_out);
+
+/*
+ * bat_reliability_range with flags: [c_lo, c_hi) in the index order the
+ * flags select.
+ */
+int bat_reliability_range_ex(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const double *p,
+                             int32_t s, int32_t t, uint32_t flags, uint64_t c_lo, uint64_t c_hi,
+                             double *R_hi, double *R_lo, uint64_t *count_out,
+                             double *T1_out, double *T0_out);
+
+/*
  * Many networks, many probability vectors, one persistent launch.
  * Graph g has n_nodes[g] nodes and the arcs arcs[arc_offsets[g] ..
  * arc_offsets[g+1]) (arc_offsets has n_graphs + 1 entries, arc_offsets[0]
@@ -225,16 +259,17 @@ int bat_last_launch(bat_launch_info *info);
 
 /*
  * The source text of the graph-specialised kernel that the library hands
- * to hiprtc for this graph: the forward sweep, or the gradient sweep when
- * grad != 0, with arc-to-counter-bit order `perm` (0..3, as "BAT_PERM").
+ * to hiprtc for this graph (flags: BAT_DIRECTED or 0): the forward sweep,
+ * or the gradient sweep when grad != 0, with arc-to-counter-bit order
+ * `perm` (0..3, as "BAT_PERM").
  * Diagnostics only; needs no GPU.  The text is what hiprtc compiles: it
  * declares no headers.  buf (may be NULL) receives at most *len bytes
  * including the terminating NUL; *len is set to the size needed.
  * Returns BAT_EINVAL on an invalid graph or perm, BAT_ETOOBIG if buf is
  * too small (nothing written).
  */
-int bat_jit_source(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, int32_t s, int32_t t, int32_t grad,
-                   int32_t perm, char *buf, uint64_t *len);
+int bat_jit_source(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, int32_t s, int32_t t, uint32_t flags,
+                   int32_t grad, int32_t perm, char *buf, uint64_t *len);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,8 @@ BAT_MAX_PVEC = 1024
 EXPORTED = ("bat_version", "bat_last_error", "bat_reliability", "bat_reliability_grad",
             "bat_reliability_range", "bat_reliability_batched", "bat_reliability_async",
             "bat_reliability_grad_async", "bat_set_option", "bat_get_option", "bat_autotune",
-            "bat_last_launch", "bat_jit_source", "bat_autotune_batched")
+            "bat_last_launch", "bat_jit_source", "bat_autotune_batched", "bat_reliability_ex",
+            "bat_reliability_range_ex")
 
 
 class bat_arc(ctypes.Structure):
@@ -75,8 +76,11 @@ def _load():
         "bat_get_option": ([ctypes.c_char_p, P], ctypes.c_int),
         "bat_autotune": ([i32, i32, P, P, i32, i32, P], ctypes.c_int),
         "bat_last_launch": ([P], ctypes.c_int),
-        "bat_jit_source": ([i32, i32, P, i32, i32, i32, i32, P, P], ctypes.c_int),
+        "bat_jit_source": ([i32, i32, P, i32, i32, ctypes.c_uint32, i32, i32, P, P], ctypes.c_int),
         "bat_autotune_batched": ([i32, P, P, P, P, P, i32, P, P], ctypes.c_int),
+        "bat_reliability_ex": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, P, P, P, P, P], ctypes.c_int),
+        "bat_reliability_range_ex": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, u64, u64, P, P, P, P, P],
+                                     ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -171,8 +175,18 @@ class RangeResult:
         return self.R_hi + self.R_lo
 
 
+BAT_DIRECTED = 1
+BAT_FORWARD_ORDER = 2
+
+
+def _flags(directed: bool, forward: bool = False) -> int:
+    return (BAT_DIRECTED if directed else 0) | (BAT_FORWARD_ORDER if forward else 0)
+
+
 def bat_reliability_range(n_nodes: int, arcs, p, s: int, t: int, c_lo: int, c_hi: int,
-                          grad: bool = False) -> RangeResult:
+                          grad: bool = False, directed: bool = False, forward: bool = False) -> RangeResult:
+    """Partial sums over indices [c_lo, c_hi): backward BAT order, or the
+    forward order (forward=True); directed=True reads arcs as u -> v."""
     a = _arcs(arcs)
     m = a.shape[0]
     pv = _p(p, m)
@@ -181,9 +195,33 @@ def bat_reliability_range(n_nodes: int, arcs, p, s: int, t: int, c_lo: int, c_hi
     cnt = ctypes.c_uint64(0)
     T1 = np.zeros(max(m, 1)) if grad else None
     T0 = np.zeros(max(m, 1)) if grad else None
-    _check(_lib.bat_reliability_range(n_nodes, m, _ptr(a), _ptr(pv), s, t, int(c_lo), int(c_hi),
-                                      ctypes.byref(hi), ctypes.byref(lo), ctypes.byref(cnt), _ptr(T1), _ptr(T0)))
+    flags = _flags(directed, forward)
+    if flags:
+        _check(_lib.bat_reliability_range_ex(n_nodes, m, _ptr(a), _ptr(pv), s, t, flags, int(c_lo), int(c_hi),
+                                             ctypes.byref(hi), ctypes.byref(lo), ctypes.byref(cnt), _ptr(T1),
+                                             _ptr(T0)))
+    else:
+        _check(_lib.bat_reliability_range(n_nodes, m, _ptr(a), _ptr(pv), s, t, int(c_lo), int(c_hi),
+                                          ctypes.byref(hi), ctypes.byref(lo), ctypes.byref(cnt), _ptr(T1), _ptr(T0)))
     return RangeResult(hi.value, lo.value, cnt.value, None if T1 is None else T1[:m], None if T0 is None else T0[:m])
+
+
+def bat_reliability_ex(n_nodes: int, arcs, p, s: int, t: int, directed: bool = False, grad: bool = False):
+    """bat_reliability / bat_reliability_grad with flags: (R, count) or a
+    GradResult."""
+    a = _arcs(arcs)
+    m = a.shape[0]
+    pv = _p(p, m)
+    R = ctypes.c_double(0.0)
+    cnt = ctypes.c_uint64(0)
+    g = np.zeros(max(m, 1)) if grad else None
+    T1 = np.zeros(max(m, 1)) if grad else None
+    T0 = np.zeros(max(m, 1)) if grad else None
+    _check(_lib.bat_reliability_ex(n_nodes, m, _ptr(a), _ptr(pv), s, t, _flags(directed), ctypes.byref(R),
+                                   ctypes.byref(cnt), _ptr(g), _ptr(T1), _ptr(T0)))
+    if not grad:
+        return R.value, cnt.value
+    return GradResult(R.value, cnt.value, g[:m], T1[:m], T0[:m])
 
 
 def _batch_args(graphs, p_blocks):
@@ -248,13 +286,15 @@ def bat_autotune(n_nodes: int, arcs, p, s: int, t: int) -> float:
     return ns.value
 
 
-def bat_jit_source(n_nodes: int, arcs, s: int, t: int, grad: bool = False, perm: int = 0) -> str:
+def bat_jit_source(n_nodes: int, arcs, s: int, t: int, grad: bool = False, perm: int = 0,
+                   directed: bool = False) -> str:
     """The hiprtc source of the graph-specialised kernel (diagnostics)."""
     a = _arcs(arcs)
     n = ctypes.c_uint64(0)
-    _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, int(grad), perm, None, ctypes.byref(n)))
+    f = _flags(directed)
+    _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, f, int(grad), perm, None, ctypes.byref(n)))
     buf = ctypes.create_string_buffer(n.value)
-    _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, int(grad), perm, buf, ctypes.byref(n)))
+    _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, f, int(grad), perm, buf, ctypes.byref(n)))
     return buf.value.decode()
 
 

@@ -166,6 +166,8 @@ struct Bcc {
 struct Plan {
     int n = 0, m = 0, s = 0, t = 0;
     int perm = 0;                         // arc -> counter bit assignment kind (0 = the paper's order)
+    bool directed = false;                // arcs are u -> v
+    bool identity = true;                 // cb_of_arc is the paper's backward order
     std::vector<int> cb_of_arc;           // counter bit of each arc
     std::vector<unsigned char> row;       // row[j] = arc at counter bit m-1-j
     int N = 0, S = 0, T = 0;              // relevant nodes, renumbered
@@ -176,9 +178,10 @@ struct Plan {
 };
 
 // Which arc sits at which counter bit.  Kind 0 is the paper's backward
-// order (arc i at bit m-1-i), the only one the range entry point uses, since
-// its indices are the paper's.  The others only reorder a full sweep (R and
-// the count are sums over all vectors):
+// order (arc i at bit m-1-i) and kind kPermForward its forward BAT order
+// (arc i at bit i): the range entry points use one of these two, since
+// their indices are the paper's.  The others only reorder a full sweep (R
+// and the count are sums over all vectors):
 //   1: the 11 in-wavefront bits (word + lane) on the relevant arcs latest in
 //      BFS order (nearest t), the 3 chained iteration bits on pruned arcs
 //      first (their warm steps are free), then on the next-latest arcs;
@@ -188,12 +191,17 @@ struct Plan {
 // Every other arc keeps the relative order of kind 0.
 constexpr int kPermKinds = 4;
 constexpr int kDefaultPerm = 3;  // untuned whole sweeps
+constexpr int kPermForward = 4;  // the forward BAT order (ranges only; never tuned)
 constexpr int kGradThreeWaveNodes = 28;  // gradient sweeps of graphs up to this size run 3 waves/SIMD
 
 void assign_bits(int m, const std::vector<int> &rel_bfs, const std::vector<char> &rel, int kind,
                  std::vector<int> &cb_of_arc)
 {
     cb_of_arc.assign(m, -1);
+    if (kind == kPermForward) {  // forward BAT (Section 4.2): arc i on counter bit i
+        for (int i = 0; i < m; ++i) cb_of_arc[i] = i;
+        return;
+    }
     if (kind == 0 || m <= bat::kWordBits) {
         for (int i = 0; i < m; ++i) cb_of_arc[i] = m - 1 - i;
         return;
@@ -230,29 +238,58 @@ void assign_bits(int m, const std::vector<int> &rel_bfs, const std::vector<char>
     for (int c = 0; c < m; ++c) cb_of_arc[by_cb[c]] = c;
 }
 
-void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, Plan &P, int perm_kind = 0)
+void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, Plan &P, int perm_kind = 0,
+               bool directed = false)
 {
     P.n = n;
     P.m = m;
     P.s = s;
     P.t = t;
     P.perm = perm_kind;
+    P.directed = directed;
     Bcc B;
     B.n = n;
     B.m = m;
-    B.adj.assign(n, {});
-    for (int i = 0; i < m; ++i) {
-        int u = arcs[i].u, v = arcs[i].v;
-        if (u == v) continue;  // a self-loop never joins two nodes
-        B.adj[u].push_back({v, i});
-        B.adj[v].push_back({u, i});
-    }
-    B.adj[s].push_back({t, m});
-    B.adj[t].push_back({s, m});
-    B.disc.assign(n, 0);
-    B.low.assign(n, 0);
     B.rel.assign(m + 1, 0);
-    B.dfs(s, -1);
+    if (!directed) {
+        B.adj.assign(n, {});
+        for (int i = 0; i < m; ++i) {
+            int u = arcs[i].u, v = arcs[i].v;
+            if (u == v) continue;  // a self-loop never joins two nodes
+            B.adj[u].push_back({v, i});
+            B.adj[v].push_back({u, i});
+        }
+        B.adj[s].push_back({t, m});
+        B.adj[t].push_back({s, m});
+        B.disc.assign(n, 0);
+        B.low.assign(n, 0);
+        B.dfs(s, -1);
+    } else {
+        // arc u -> v can only matter when s reaches u and v reaches t, and
+        // it neither enters s nor leaves t (a superset of the arcs on simple
+        // s -> t paths, which is hard to decide exactly for digraphs)
+        std::vector<char> from_s(n, 0), to_t(n, 0);
+        std::vector<int> q{s};
+        from_s[s] = 1;
+        for (size_t h = 0; h < q.size(); ++h)
+            for (int i = 0; i < m; ++i)
+                if (arcs[i].u == q[h] && !from_s[arcs[i].v]) {
+                    from_s[arcs[i].v] = 1;
+                    q.push_back(arcs[i].v);
+                }
+        q.assign(1, t);
+        to_t[t] = 1;
+        for (size_t h = 0; h < q.size(); ++h)
+            for (int i = 0; i < m; ++i)
+                if (arcs[i].v == q[h] && !to_t[arcs[i].u]) {
+                    to_t[arcs[i].u] = 1;
+                    q.push_back(arcs[i].u);
+                }
+        for (int i = 0; i < m; ++i) {
+            const int u = arcs[i].u, v = arcs[i].v;
+            B.rel[i] = u != v && v != s && u != t && from_s[u] && to_t[v];
+        }
+    }
 
     // BFS from s over relevant arcs: node numbering and sweep order
     std::vector<int> id(n, -1), order, rel_bfs, disc_flag;
@@ -265,7 +302,7 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
         for (int i = 0; i < m; ++i) {
             if (!B.rel[i] || listed[i]) continue;
             int a = arcs[i].u, b = arcs[i].v;
-            if (a != u && b != u) continue;
+            if (directed ? a != u : (a != u && b != u)) continue;  // directed: leave by the tail
             int w = (a == u) ? b : a;
             int discovers = 0;
             if (id[w] < 0) {
@@ -283,8 +320,9 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
         id[t] = (int)order.size();
         order.push_back(t);
     }
+    // relevant = swept: an arc the search from s never lists cannot matter
     std::vector<char> rel(m, 0);
-    for (int i = 0; i < m; ++i) rel[i] = B.rel[i];
+    for (int i = 0; i < m; ++i) rel[i] = listed[i];
     assign_bits(m, rel_bfs, rel, perm_kind, P.cb_of_arc);
     {  // must be a bijection onto [0, m); otherwise use the paper's order
         std::vector<char> hit(std::max(m, 1), 0);
@@ -299,6 +337,9 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
             for (int i = 0; i < m; ++i) P.cb_of_arc[i] = m - 1 - i;
         }
     }
+    P.identity = true;  // the paper's backward order: arc i on counter bit m - 1 - i
+    for (int i = 0; i < m; ++i)
+        if (P.cb_of_arc[i] != m - 1 - i) P.identity = false;
     P.row.assign(std::max(m, 1), 0);
     for (int i = 0; i < m; ++i) P.row[m - 1 - P.cb_of_arc[i]] = (unsigned char)i;
     P.ru.clear(); P.rv.clear(); P.rb.clear(); P.rd.clear();
@@ -331,7 +372,7 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
             P.prog[ng * 8 + 2 * kb + 1] = P.wconst[k];
         }
     }
-    std::string sdesc = "N" + std::to_string(P.N) + " S" + std::to_string(P.S) + " T" + std::to_string(P.T) +
+    std::string sdesc = std::string(directed ? "D " : "") + "N" + std::to_string(P.N) + " S" + std::to_string(P.S) + " T" + std::to_string(P.T) +
                         " m" + std::to_string(m) + " :";
     for (size_t k = 0; k < P.ru.size(); ++k)
         sdesc += " " + std::to_string(P.ru[k]) + "," + std::to_string(P.rv[k]) + "," + std::to_string(P.rb[k]) +
@@ -437,6 +478,7 @@ std::string jit_source(const Plan &P, bool grad)
     arr("RV", P.rv);
     arr("RB", P.rb);
     arr("RD", P.rd);
+    s += std::string("  static constexpr bool DIR = ") + (P.directed ? "true" : "false") + ";\n";
     // relaxations of counter bits 11..16 (the chained iteration arcs)
     int ck[6] = {-1, -1, -1, -1, -1, -1};
     for (size_t k = 0; k < nr; ++k)
@@ -513,9 +555,10 @@ std::map<std::string, TuneChoice> g_tune;
 
 // The graph itself (node count, arcs, terminals): what tuned choices are
 // remembered under.
-std::string graph_key(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t)
+std::string graph_key(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, bool directed = false)
 {
-    std::string k = std::to_string(n) + "/" + std::to_string(s) + "/" + std::to_string(t) + ":";
+    std::string k = std::string(directed ? "D" : "") + std::to_string(n) + "/" + std::to_string(s) + "/" +
+                    std::to_string(t) + ":";
     for (int32_t i = 0; i < m; ++i) k += std::to_string(arcs[i].u) + "-" + std::to_string(arcs[i].v) + ",";
     return k;
 }
@@ -680,7 +723,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
         maps[64 + i] = (unsigned char)P.cb_of_arc[i];
     }
     HIPCHK(hipMemcpyAsync(ws + o_map, maps, sizeof maps, hipMemcpyHostToDevice, stream));
-    const bool identity = P.perm == 0 || P.m <= bat::kWordBits;
+    const bool identity = P.identity;
     const unsigned char *d_row = identity ? nullptr : (const unsigned char *)(ws + o_map);
     L.cb_of_arc = identity ? nullptr : (const unsigned char *)(ws + o_map + 64);
     if (!P.prog.empty())
@@ -704,7 +747,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
         void *args[] = {&K};
         HIPCHK(hipModuleLaunchKernel(jfn, (unsigned)blocks, 1, 1, bat::kBlock, 1, 1, 0, stream, args, nullptr));
     } else {
-        HIPCHK(batk::sweep_dyn(stream, (unsigned)blocks, rq.grad, P.N, K));
+        HIPCHK(batk::sweep_dyn(stream, (unsigned)blocks, rq.grad, P.N, P.directed, K));
     }
     HIPCHK(hipEventRecord(t_state.ev[2], stream));
     HIPCHK(batk::reduce(stream, (const double *)K.part, (const u64 *)K.pcount, K.n_chunks, K.ncol, L.res, L.count));
@@ -731,16 +774,18 @@ struct Prepared {
 // Validate, pick the launch choices and plan.  full_range: the whole
 // counter, where any arc order may be used; otherwise the paper's order.
 int prepare(int32_t n, int32_t m, const bat_arc *arcs, const double *p_host, int32_t s, int32_t t, bool grad,
-            bool full_range, const Request *forced, Prepared &X, TuneChoice &tc)
+            bool full_range, const Request *forced, Prepared &X, TuneChoice &tc, uint32_t flags = 0)
 {
     int rc = validate(n, m, arcs, p_host, s, t);
     if (rc) return rc;
     rc = current_device(X.D);
     if (rc) return rc;
-    tc = choose(X.D, graph_key(n, m, arcs, s, t), grad, forced);
-    if (tc.perm < 0 || tc.perm >= kPermKinds) tc.perm = kDefaultPerm;
-    if (!full_range) tc.perm = 0;
-    make_plan(n, m, arcs, s, t, X.P, tc.perm);
+    const bool directed = (flags & BAT_DIRECTED) != 0;
+    tc = choose(X.D, graph_key(n, m, arcs, s, t, directed), grad, forced);
+    const bool forward = forced && forced->force_perm == kPermForward;
+    if (!forward && (tc.perm < 0 || tc.perm >= kPermKinds)) tc.perm = kDefaultPerm;
+    if (!full_range && !forward) tc.perm = 0;
+    make_plan(n, m, arcs, s, t, X.P, tc.perm, directed);
     return BAT_OK;
 }
 
@@ -748,7 +793,7 @@ int prepare(int32_t n, int32_t m, const bat_arc *arcs, const double *p_host, int
 // count and the plan's arc -> counter bit map (for the gradient columns).
 int run_sync(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t, u64 c_lo,
              u64 c_hi, bool grad, std::vector<double> &res, u64 &count, Request *tmpl = nullptr,
-             std::vector<int> *cb_of_arc = nullptr)
+             std::vector<int> *cb_of_arc = nullptr, uint32_t flags = 0)
 {
     Prepared X;
     TuneChoice tc;
@@ -757,7 +802,7 @@ int run_sync(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t
     // any arc order for a whole sweep; a partial range is in the paper's
     // order unless the caller (the autotuner timing a sample) forces one
     const bool allow_perm = full || (tmpl && tmpl->force_perm >= 0);
-    int rc = prepare(n, m, arcs, p, s, t, grad, allow_perm, tmpl, X, tc);
+    int rc = prepare(n, m, arcs, p, s, t, grad, allow_perm, tmpl, X, tc, flags);
     if (rc) return rc;
     rc = thread_stream(X.D.id, X.stream);
     if (rc) return rc;
@@ -825,45 +870,52 @@ int bat_get_option(const char *key, int64_t *value)
     return BAT_OK;
 }
 
-int bat_reliability(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
-                    double *R_out, uint64_t *count_out)
+int bat_reliability_ex(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                       uint32_t flags, double *R_out, uint64_t *count_out, double *dRdp_out, double *T1_out,
+                       double *T0_out)
 {
     t_err.clear();
     if (!R_out || !count_out) return fail(BAT_EINVAL, "NULL output pointer");
+    if (flags & ~(uint32_t)(BAT_DIRECTED | BAT_FORWARD_ORDER)) return fail(BAT_EINVAL, "unknown flags 0x%x", flags);
     if (m < 0 || m > BAT_MAX_ARCS) return validate(n, m, arcs, p, s, t);
+    const bool grad = dRdp_out || T1_out || T0_out;
     std::vector<double> res;
+    std::vector<int> cba;
     u64 cnt = 0;
-    int rc = run_sync(n, m, arcs, p, s, t, 0, 1ull << m, false, res, cnt);
+    // a whole sweep: the index order does not matter, any arc order is used
+    int rc = run_sync(n, m, arcs, p, s, t, 0, 1ull << m, grad, res, cnt, nullptr, &cba, flags);
     if (rc) return rc;
     *R_out = res[0] + res[1];
     *count_out = cnt;
+    if (grad) split_grad(res, cba, m, dRdp_out, T1_out, T0_out);
     return BAT_OK;
+}
+
+int bat_reliability(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                    double *R_out, uint64_t *count_out)
+{
+    return bat_reliability_ex(n, m, arcs, p, s, t, 0u, R_out, count_out, nullptr, nullptr, nullptr);
 }
 
 int bat_reliability_grad(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
                          double *R_out, uint64_t *count_out, double *dRdp_out, double *T1_out, double *T0_out)
 {
     t_err.clear();
-    if (!R_out || !count_out || (!dRdp_out && m > 0)) return fail(BAT_EINVAL, "NULL output pointer");
-    if (m < 0 || m > BAT_MAX_ARCS) return validate(n, m, arcs, p, s, t);
-    std::vector<double> res;
-    std::vector<int> cba;
-    u64 cnt = 0;
-    int rc = run_sync(n, m, arcs, p, s, t, 0, 1ull << m, true, res, cnt, nullptr, &cba);
-    if (rc) return rc;
-    *R_out = res[0] + res[1];
-    *count_out = cnt;
-    split_grad(res, cba, m, dRdp_out, T1_out, T0_out);
-    return BAT_OK;
+    if (!dRdp_out && m > 0) return fail(BAT_EINVAL, "NULL output pointer");
+    if (m == 0) {  // no arcs: no gradient to write, R = 0 from the forward sweep
+        return bat_reliability_ex(n, m, arcs, p, s, t, 0u, R_out, count_out, nullptr, nullptr, nullptr);
+    }
+    return bat_reliability_ex(n, m, arcs, p, s, t, 0u, R_out, count_out, dRdp_out, T1_out, T0_out);
 }
 
-int bat_reliability_range(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
-                          uint64_t c_lo, uint64_t c_hi, double *R_hi, double *R_lo, uint64_t *count_out,
-                          double *T1_out, double *T0_out)
+int bat_reliability_range_ex(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                             uint32_t flags, uint64_t c_lo, uint64_t c_hi, double *R_hi, double *R_lo,
+                             uint64_t *count_out, double *T1_out, double *T0_out)
 {
     t_err.clear();
     if (!R_hi || !R_lo || !count_out) return fail(BAT_EINVAL, "NULL output pointer");
     if ((T1_out == nullptr) != (T0_out == nullptr)) return fail(BAT_EINVAL, "T1_out and T0_out must both be set or both NULL");
+    if (flags & ~(uint32_t)(BAT_DIRECTED | BAT_FORWARD_ORDER)) return fail(BAT_EINVAL, "unknown flags 0x%x", flags);
     if (m < 0 || m > BAT_MAX_ARCS) return validate(n, m, arcs, p, s, t);
     if (c_lo > c_hi || c_hi > (1ull << m)) return fail(BAT_EINVAL, "bad range [%llu, %llu) for m = %d",
                                                      (unsigned long long)c_lo, (unsigned long long)c_hi, m);
@@ -880,15 +932,23 @@ int bat_reliability_range(int32_t n, int32_t m, const bat_arc *arcs, const doubl
     std::vector<double> res;
     std::vector<int> cba;
     u64 cnt = 0;
-    Request paper_order{};
-    paper_order.force_perm = 0;  // indices are the paper's backward order
-    int rc = run_sync(n, m, arcs, p, s, t, c_lo, c_hi, grad, res, cnt, &paper_order, &cba);
+    Request order{};
+    // the indices are the paper's: backward BAT (Eq. 2-3) or forward (Eq. 4-5)
+    order.force_perm = (flags & BAT_FORWARD_ORDER) ? kPermForward : 0;
+    int rc = run_sync(n, m, arcs, p, s, t, c_lo, c_hi, grad, res, cnt, &order, &cba, flags);
     if (rc) return rc;
     *R_hi = res[0];
     *R_lo = res[1];
     *count_out = cnt;
     if (grad) split_grad(res, cba, m, nullptr, T1_out, T0_out);
     return BAT_OK;
+}
+
+int bat_reliability_range(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                          uint64_t c_lo, uint64_t c_hi, double *R_hi, double *R_lo, uint64_t *count_out,
+                          double *T1_out, double *T0_out)
+{
+    return bat_reliability_range_ex(n, m, arcs, p, s, t, 0u, c_lo, c_hi, R_hi, R_lo, count_out, T1_out, T0_out);
 }
 
 static int async_common(int32_t n, int32_t m, const bat_arc *arcs, const double *p_dev, int32_t s, int32_t t,
@@ -947,16 +1007,17 @@ int bat_last_launch(bat_launch_info *info)
     return BAT_OK;
 }
 
-int bat_jit_source(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, int32_t grad, int32_t perm,
-                   char *buf, uint64_t *len)
+int bat_jit_source(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, uint32_t flags, int32_t grad,
+                   int32_t perm, char *buf, uint64_t *len)
 {
     t_err.clear();
     if (!len) return fail(BAT_EINVAL, "len is NULL");
+    if (flags & ~(uint32_t)BAT_DIRECTED) return fail(BAT_EINVAL, "unknown flags 0x%x", flags);
     int rc = validate(n, m, arcs, nullptr, s, t);
     if (rc) return rc;
     if (perm < 0 || perm >= kPermKinds) return fail(BAT_EINVAL, "perm %d outside [0, %d)", perm, kPermKinds);
     Plan P;
-    make_plan(n, m, arcs, s, t, P, perm);
+    make_plan(n, m, arcs, s, t, P, perm, (flags & BAT_DIRECTED) != 0);
     const std::string src = jit_source(P, grad != 0);
     const uint64_t need = (uint64_t)src.size() + 1;
     const uint64_t have = *len;

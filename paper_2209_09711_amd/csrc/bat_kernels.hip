@@ -1,9 +1,10 @@
 // bat_kernels.hip -- ahead-of-time kernels of the BAT reliability library.
 //
 //  k_build_tables : the probability factor tables of Eq. 1 from p (device).
-//  k_fwd_dyn<N>   : enumeration + connectivity + Pr sum, graph read at run
-//                   time (N = register budget for node reach words).
-//  k_grad_dyn<N>  : the same sweep also producing T1_i / T0_i per arc.
+//  k_fwd_dyn<N,D> : enumeration + connectivity + Pr sum, graph read at run
+//                   time (N = register budget for node reach words, D =
+//                   directed arcs).
+//  k_grad_dyn<N,D>: the same sweep also producing T1_i / T0_i per arc.
 //  k_reduce       : fixed-order double-double sum of per-work-item partials.
 //  k_finalize     : results to the caller's device buffers.
 //  k_batched_dyn  : many graphs x many probability vectors, persistent.
@@ -106,27 +107,33 @@ k_build_tables(const double *__restrict__ p, const unsigned char *__restrict__ r
     build_tables_dev(pr, m, f, T, true);
 }
 
-template <int NMAX>
+template <int NMAX, bool DIR>
 __global__ void __launch_bounds__(256) k_fwd_dyn(bat::KParams P)
 {
     __shared__ bat::LdsTables L;
-    bat::sweep_kernel<bat::DynClosure<NMAX>, false>(P, L, nullptr);
+    bat::sweep_kernel<bat::DynClosure<NMAX, DIR>, false>(P, L, nullptr);
 }
 
-template <int NMAX>
+template <int NMAX, bool DIR>
 __global__ void __launch_bounds__(256) k_grad_dyn(bat::KParams P)
 {
     __shared__ bat::LdsTables L;
     __shared__ bat::LdsGrad LG;
-    bat::sweep_kernel<bat::DynClosure<NMAX>, true>(P, L, &LG);
+    bat::sweep_kernel<bat::DynClosure<NMAX, DIR>, true>(P, L, &LG);
 }
 
-template __global__ void k_fwd_dyn<16>(bat::KParams);
-template __global__ void k_fwd_dyn<32>(bat::KParams);
-template __global__ void k_fwd_dyn<64>(bat::KParams);
-template __global__ void k_grad_dyn<16>(bat::KParams);
-template __global__ void k_grad_dyn<32>(bat::KParams);
-template __global__ void k_grad_dyn<64>(bat::KParams);
+template __global__ void k_fwd_dyn<16, false>(bat::KParams);
+template __global__ void k_fwd_dyn<32, false>(bat::KParams);
+template __global__ void k_fwd_dyn<64, false>(bat::KParams);
+template __global__ void k_grad_dyn<16, false>(bat::KParams);
+template __global__ void k_grad_dyn<32, false>(bat::KParams);
+template __global__ void k_grad_dyn<64, false>(bat::KParams);
+template __global__ void k_fwd_dyn<16, true>(bat::KParams);
+template __global__ void k_fwd_dyn<32, true>(bat::KParams);
+template __global__ void k_fwd_dyn<64, true>(bat::KParams);
+template __global__ void k_grad_dyn<16, true>(bat::KParams);
+template __global__ void k_grad_dyn<32, true>(bat::KParams);
+template __global__ void k_grad_dyn<64, true>(bat::KParams);
 
 // Column col of the partials: block col sums it over all work items in a
 // fixed order (thread-strided, then a fixed tree), so the result does not
@@ -373,19 +380,26 @@ hipError_t build_tables(hipStream_t st, const double *p, const unsigned char *ro
     return hipGetLastError();
 }
 
-hipError_t sweep_dyn(hipStream_t st, unsigned blocks, bool grad, int nmax, const bat::KParams &K)
+template <bool DIR>
+static void sweep_dyn_t(hipStream_t st, unsigned blocks, bool grad, int nmax, const bat::KParams &K)
 {
     const dim3 g(blocks), b(bat::kBlock);
     if (nmax <= 16) {
-        if (grad) hipLaunchKernelGGL(k_grad_dyn<16>, g, b, 0, st, K);
-        else hipLaunchKernelGGL(k_fwd_dyn<16>, g, b, 0, st, K);
+        if (grad) hipLaunchKernelGGL((k_grad_dyn<16, DIR>), g, b, 0, st, K);
+        else hipLaunchKernelGGL((k_fwd_dyn<16, DIR>), g, b, 0, st, K);
     } else if (nmax <= 32) {
-        if (grad) hipLaunchKernelGGL(k_grad_dyn<32>, g, b, 0, st, K);
-        else hipLaunchKernelGGL(k_fwd_dyn<32>, g, b, 0, st, K);
+        if (grad) hipLaunchKernelGGL((k_grad_dyn<32, DIR>), g, b, 0, st, K);
+        else hipLaunchKernelGGL((k_fwd_dyn<32, DIR>), g, b, 0, st, K);
     } else {
-        if (grad) hipLaunchKernelGGL(k_grad_dyn<64>, g, b, 0, st, K);
-        else hipLaunchKernelGGL(k_fwd_dyn<64>, g, b, 0, st, K);
+        if (grad) hipLaunchKernelGGL((k_grad_dyn<64, DIR>), g, b, 0, st, K);
+        else hipLaunchKernelGGL((k_fwd_dyn<64, DIR>), g, b, 0, st, K);
     }
+}
+
+hipError_t sweep_dyn(hipStream_t st, unsigned blocks, bool grad, int nmax, bool directed, const bat::KParams &K)
+{
+    if (directed) sweep_dyn_t<true>(st, blocks, grad, nmax, K);
+    else sweep_dyn_t<false>(st, blocks, grad, nmax, K);
     return hipGetLastError();
 }
 

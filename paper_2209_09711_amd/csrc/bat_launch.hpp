@@ -52,7 +52,7 @@ hipError_t batched_reduce(hipStream_t st, const BatchEntry *entries, unsigned n_
 
 hipError_t build_tables(hipStream_t st, const double *p, const unsigned char *row, bat::u32 m, bat::u32 f,
                         double *T, int *status);
-hipError_t sweep_dyn(hipStream_t st, unsigned blocks, bool grad, int nmax, const bat::KParams &K);
+hipError_t sweep_dyn(hipStream_t st, unsigned blocks, bool grad, int nmax, bool directed, const bat::KParams &K);
 hipError_t reduce(hipStream_t st, const double *part, const bat::u64 *pcount, bat::u64 n_chunks, bat::u32 ncol,
                   double *res, bat::u64 *count);
 hipError_t finalize(hipStream_t st, const double *res, const bat::u64 *count, const int *status,

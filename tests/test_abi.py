@@ -115,9 +115,11 @@ def test_jit_sources_compile(tmp_path, grad):
     loops.arcs = loops.arcs + [(0, 0), (3, 3)]
     # a 34-node cycle: more relevant nodes than the register-resident budget
     cycle = W.Network("cycle34", 34, [(i, (i + 1) % 34) for i in range(34)], 0, 17, np.full(34, 0.9))
-    cases = [(W.config4(), 3, True), (W.config2(), 0, True), (loops, 1, True), (cycle, 2, False)]
-    for k, (net, perm, small) in enumerate(cases):
-        src = B.bat_jit_source(net.n, net.arcs, net.s, net.t, grad=grad, perm=perm)
+    cases = [(W.config4(), 3, True, False), (W.config2(), 0, True, False), (loops, 1, True, False),
+             (cycle, 2, False, False), (W.config4(), 3, True, True)]
+    for k, (net, perm, small, directed) in enumerate(cases):
+        src = B.bat_jit_source(net.n, net.arcs, net.s, net.t, grad=grad, perm=perm, directed=directed)
+        assert ("DIR = true" in src) == directed
         assert "struct JitGraph" in src and ("bat_grad_jit" if grad else "bat_fwd_jit") in src
         f = tmp_path / f"k{k}.hip"
         f.write_text("#include <hip/hip_runtime.h>\n" + src)
@@ -130,7 +132,37 @@ def test_jit_sources_compile(tmp_path, grad):
         priv = [int(x) for x in re.findall(r"\.private_segment_fixed_size:\s+(\d+)", asm)]
         spill = [int(x) for x in re.findall(r"\.vgpr_spill_count:\s+(\d+)", asm)]
         assert priv and spill
-        if small:
+        if small and not grad:
             assert max(priv) == 0 and max(spill) == 0, (net.name, priv, spill)
+        if small:
+            # the gradient build asks for three wavefronts per SIMD: it may
+            # spill, but only in once-per-block or once-per-item code, never
+            # inside the per-iteration loops (loop depth >= 2)
+            depth, inner = 0, []
+            for line in asm.splitlines():
+                if re.match(r"^(\.LBB\d+_\d+:|; %bb\.\d+:)", line):  # every block start
+                    mm = re.search(r"Depth=(\d+)", line)
+                    depth = int(mm.group(1)) if mm else 0
+                if "scratch_" in line and depth >= 2:
+                    inner.append(line.strip())
+            assert not inner, (net.name, directed, inner[:4])
     with pytest.raises(B.BatError):
         B.bat_jit_source(3, [(0, 1), (1, 2)], 0, 2, perm=9)
+
+
+def test_flag_validation_without_device():
+    """Unknown flag bits are rejected before any device work."""
+    import paper_2209_09711_amd as B
+    a = np.asarray([[0, 1], [1, 2]], dtype=np.int32)
+    p = np.full(2, 0.5)
+    R = ctypes.c_double(0.0)
+    cnt = ctypes.c_uint64(0)
+    rc = B._lib.bat_reliability_ex(3, 2, B._ptr(a), B._ptr(p), 0, 2, 8, ctypes.byref(R), ctypes.byref(cnt),
+                                   None, None, None)
+    assert rc == -1 and "flags" in B.bat_last_error()
+    hi = ctypes.c_double(0.0)
+    lo = ctypes.c_double(0.0)
+    rc = B._lib.bat_reliability_range_ex(3, 2, B._ptr(a), B._ptr(p), 0, 2, 4, 0, 4, ctypes.byref(hi),
+                                         ctypes.byref(lo), ctypes.byref(cnt), None, None)
+    assert rc == -1 and "flags" in B.bat_last_error()
+    assert B.BAT_DIRECTED == 1 and B.BAT_FORWARD_ORDER == 2

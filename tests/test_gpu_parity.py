@@ -440,6 +440,100 @@ def test_autotune_choice_keeps_results():
     assert g.count == c0 and rel_ok(g.R, R0)
 
 
+# ------------------------------------------------------- directed, forward
+
+def _digraph(seed, n, m):
+    """A random digraph with a good chance of s -> t paths: a random
+    connected graph, each arc oriented at random, plus reversed copies of
+    a third of them."""
+    rng = np.random.default_rng(seed)
+    net = W.random_connected(n, m, seed=seed, p_lo=0.3, p_hi=0.95)
+    arcs = [(u, v) if rng.random() < 0.5 else (v, u) for (u, v) in net.arcs]
+    extra = [(v, u) for (u, v) in arcs if rng.random() < 1 / 3]
+    arcs = arcs + extra
+    p = rng.uniform(0.3, 0.95, size=len(arcs))
+    return net.n, arcs, p, net.s, net.t
+
+
+def test_directed_bridge():
+    """The directed bridge (arcs as listed, u -> v) at p = 0.9: the oracle's
+    pin, R = 0.97119, 15 connected vectors."""
+    B = _B()
+    arcs = [(0, 1), (0, 2), (1, 2), (1, 3), (2, 3)]
+    R, c = B.bat_reliability_ex(4, arcs, np.full(5, 0.9), 0, 3, directed=True)
+    o = oracle.reliability(4, arcs, np.full(5, 0.9), 0, 3, directed=True)
+    assert c == o.count == 15 and rel_ok(R, o.sum) and abs(R - 0.97119) < 5e-6
+
+
+@pytest.mark.parametrize("jit", [0, 1])
+def test_directed_vs_oracle(jit):
+    """Directed sweeps (generic and specialised kernels) against the
+    directed oracle: whole sweeps with the gradient, and ranges."""
+    B = _B()
+    for seed, n, m in [(31, 8, 14), (32, 10, 18), (33, 12, 17)]:
+        nn, arcs, p, s, t = _digraph(seed, n, m)
+        say("directed", seed, len(arcs), "jit", jit)
+        with options(BAT_JIT=jit):
+            g = B.bat_reliability_ex(nn, arcs, p, s, t, directed=True, grad=True)
+            o = oracle.reliability(nn, arcs, p, s, t, grad=True, directed=True)
+            assert g.count == o.count and rel_ok(g.R, o.sum)
+            assert np.allclose(g.T1, o.T1, rtol=1e-12, atol=1e-300)
+            assert np.allclose(g.T0, o.T0, rtol=1e-12, atol=1e-300)
+            u = B.bat_reliability_ex(nn, arcs, p, s, t, directed=False)
+            ou = oracle.reliability(nn, arcs, p, s, t)
+            assert u[1] == ou.count and rel_ok(u[0], ou.sum)
+            M = 1 << len(arcs)
+            for lo, hi in [(0, M // 3), (M // 3 + 5, M - 7)]:
+                r = B.bat_reliability_range(nn, arcs, p, s, t, lo, hi, grad=True, directed=True)
+                orr = oracle.reliability_range(nn, arcs, p, s, t, lo, hi, grad=True, directed=True)
+                assert r.count == orr.count and rel_ok(r.R, orr.sum)
+
+
+@pytest.mark.parametrize("k", [0, 3, 5])
+def test_directed_chains_large(k):
+    """A larger digraph: warm-started chains (one-directional consistency
+    test) against ranges of the directed oracle and the exact count split."""
+    B = _B()
+    nn, arcs, p, s, t = _digraph(77, 14, 22)
+    M = 1 << len(arcs)
+    with options(BAT_CHAIN_LOG2=k, BAT_JIT=1):
+        say("directed chains", k, len(arcs))
+        R, c = B.bat_reliability_ex(nn, arcs, p, s, t, directed=True)
+        parts = [B.bat_reliability_range(nn, arcs, p, s, t, a, b, directed=True)
+                 for a, b in [(0, M // 2), (M // 2, M)]]
+        assert sum(x.count for x in parts) == c
+        assert rel_ok(sum(x.R for x in parts), R)
+        rng = np.random.default_rng(k)
+        for _ in range(3):
+            lo = int(rng.integers(0, M - (1 << 18)))
+            hi = lo + int(rng.integers(1, 1 << 18))
+            r = B.bat_reliability_range(nn, arcs, p, s, t, lo, hi, directed=True)
+            o = oracle.reliability_range(nn, arcs, p, s, t, lo, hi, directed=True)
+            assert r.count == o.count and rel_ok(r.R, o.sum)
+    with options(BAT_JIT=0, BAT_CHAIN_LOG2=k):
+        R0, c0 = B.bat_reliability_ex(nn, arcs, p, s, t, directed=True)
+    assert c0 == c and rel_ok(R0, R)
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_forward_order_ranges(directed):
+    """Ranges in the forward BAT order (Eq. 4-5) against the oracle's
+    forward order, including ranges that split the word, lane and chained
+    bits; the two orders' whole sweeps agree."""
+    B = _B()
+    net = W.random_connected(13, 26, seed=91 + directed, p_lo=0.3, p_hi=0.99)
+    arcs, p = net.arcs, net.p
+    M = 1 << len(arcs)
+    for lo, hi in [(0, 1000), (12345, 12345 + 3 * (1 << 13) + 77), (M // 2 - 999, M // 2 + (1 << 20)), (M - 4097, M)]:
+        r = B.bat_reliability_range(net.n, arcs, p, net.s, net.t, lo, hi, grad=True, directed=directed, forward=True)
+        o = oracle.reliability_range(net.n, arcs, p, net.s, net.t, lo, hi, grad=True, directed=directed, forward=True)
+        assert r.count == o.count and rel_ok(r.R, o.sum), (lo, hi)
+        assert np.allclose(r.T1, o.T1, rtol=1e-12, atol=1e-300) and np.allclose(r.T0, o.T0, rtol=1e-12, atol=1e-300)
+    f = B.bat_reliability_range(net.n, arcs, p, net.s, net.t, 0, M, directed=directed, forward=True)
+    b = B.bat_reliability_range(net.n, arcs, p, net.s, net.t, 0, M, directed=directed)
+    assert f.count == b.count and rel_ok(f.R, b.R)
+
+
 # ------------------------------------------------------------------- torch
 
 def test_torch_autograd_and_async():
