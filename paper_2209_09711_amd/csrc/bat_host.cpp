@@ -193,6 +193,7 @@ constexpr int kPermKinds = 4;
 constexpr int kDefaultPerm = 3;  // untuned whole sweeps
 constexpr int kPermForward = 4;  // the forward BAT order (ranges only; never tuned)
 constexpr int kGradThreeWaveNodes = 28;  // gradient sweeps of graphs up to this size run 3 waves/SIMD
+constexpr int kSuperMaxNodes = 28;       // forward sweeps keep super-block bottoms in LDS up to this size
 
 void assign_bits(int m, const std::vector<int> &rel_bfs, const std::vector<char> &rel, int kind,
                  std::vector<int> &cb_of_arc)
@@ -479,6 +480,10 @@ std::string jit_source(const Plan &P, bool grad)
     arr("RB", P.rb);
     arr("RD", P.rd);
     s += std::string("  static constexpr bool DIR = ") + (P.directed ? "true" : "false") + ";\n";
+    // forward sweeps of graphs small enough for the LDS store (4 blocks of
+    // 4 wavefronts per CU keep (N + 2) words per lane each) also resume
+    // block bottoms from the kept bottom of their 2^6-aligned super-block
+    s += std::string("  static constexpr bool SUPER = ") + (!grad && P.N <= kSuperMaxNodes ? "true" : "false") + ";\n";
     // relaxations of counter bits 11..16 (the chained iteration arcs)
     int ck[6] = {-1, -1, -1, -1, -1, -1};
     for (size_t k = 0; k < nr; ++k)
