@@ -523,7 +523,7 @@ def test_directed_chains_large(k):
     """A larger digraph: warm-started chains (one-directional consistency
     test) against ranges of the directed oracle and the exact count split."""
     B = _B()
-    nn, arcs, p, s, t = _digraph(77, 14, 22)
+    nn, arcs, p, s, t = _digraph(80, 14, 22)
     M = 1 << len(arcs)
     with options(BAT_CHAIN_LOG2=k, BAT_JIT=1):
         say("directed chains", k, len(arcs))
