@@ -221,7 +221,19 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
  *                      cover distant parts of the counter), 0 = counter
  *                      order; R and counts never depend on it beyond
  *                      floating-point rounding
+ *   "BAT_JIT_FLUSH"    setting it to a nonzero value unloads every
+ *                      graph-specialised kernel this process compiled or
+ *                      loaded (after the current device finishes its work;
+ *                      no asynchronous call using one may still be pending
+ *                      on another device); reads as 0
  * Unknown keys return BAT_EINVAL.
+ *
+ * Compiled specialised kernels are also kept on disk across processes:
+ * code objects keyed by hashes of the whole kernel source, the target and
+ * the compile options, in $BAT_JIT_CACHE_DIR, else
+ * $XDG_CACHE_HOME/bat-mi355x, else $HOME/.cache/bat-mi355x.  Set the
+ * environment variable BAT_JIT_CACHE=0 to turn this off.  An entry that
+ * fails to read or load is recompiled and rewritten.
  */
 int bat_set_option(const char *key, int64_t value);
 int bat_get_option(const char *key, int64_t *value);

@@ -27,6 +27,9 @@
 #include <string>
 #include <vector>
 
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include "bat.h"
 #include "bat_launch.hpp"
 
@@ -64,7 +67,8 @@ int fail(int code, const char *fmt, ...)
 
 // ------------------------------------------------------------ options
 struct Options {
-    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1};
+    std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
+        jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -91,6 +95,7 @@ struct Options {
         if (!strcmp(k, "BAT_PERM")) return &perm;
         if (!strcmp(k, "BAT_CHAIN_LOG2")) return &chain_log2;
         if (!strcmp(k, "BAT_ITEM_ORDER")) return &item_order;
+        if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
 };
@@ -458,6 +463,93 @@ struct JitEntry {
 std::mutex g_jit_mu;
 std::map<std::string, JitEntry> g_jit;
 
+// Drop every compiled kernel of this process (modules unloaded) after the
+// current device has finished its work.
+void jit_flush()
+{
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lk(g_jit_mu);
+    for (auto &kv : g_jit)
+        if (kv.second.mod) (void)hipModuleUnload(kv.second.mod);
+    g_jit.clear();
+}
+
+// ---------------------------------------------------- on-disk code cache
+// Compiled code objects are kept across processes, keyed by two
+// independent 64-bit hashes of the whole source text, the target and the
+// compile options, so a changed kernel is never served stale.  Directory:
+// BAT_JIT_CACHE_DIR, else $XDG_CACHE_HOME/bat-mi355x, else
+// $HOME/.cache/bat-mi355x; BAT_JIT_CACHE=0 turns it off.  Anything that
+// fails to read, write or load falls back to compiling.
+struct CacheKey {
+    uint64_t h1, h2, len;
+};
+CacheKey cache_key(const std::string &text)
+{
+    uint64_t a = 1469598103934665603ull, b = 0x9E3779B97F4A7C15ull;
+    for (unsigned char c : text) {
+        a = (a ^ c) * 1099511628211ull;           // FNV-1a
+        b = (b + c) * 0xBF58476D1CE4E5B9ull;       // multiply-add, then mix
+        b ^= b >> 31;
+    }
+    return {a, b, (uint64_t)text.size()};
+}
+std::string cache_dir()
+{
+    const char *on = getenv("BAT_JIT_CACHE");
+    if (on && !strcmp(on, "0")) return "";
+    std::string d;
+    if (const char *e = getenv("BAT_JIT_CACHE_DIR"); e && *e) {
+        d = e;
+    } else if (const char *x = getenv("XDG_CACHE_HOME"); x && *x) {
+        d = std::string(x) + "/bat-mi355x";
+    } else if (const char *h = getenv("HOME"); h && *h) {
+        d = std::string(h) + "/.cache";
+        mkdir(d.c_str(), 0755);
+        d += "/bat-mi355x";
+    } else {
+        return "";
+    }
+    mkdir(d.c_str(), 0755);  // may exist already
+    struct stat st;
+    if (stat(d.c_str(), &st) != 0 || !S_ISDIR(st.st_mode)) return "";
+    return d;
+}
+std::string cache_path(const std::string &dir, const CacheKey &k)
+{
+    char name[64];
+    snprintf(name, sizeof name, "/%016llx.co", (unsigned long long)k.h1);
+    return dir + name;
+}
+constexpr char kCacheMagic[8] = {'B', 'A', 'T', 'J', 'I', 'T', '1', '\n'};
+bool cache_read(const std::string &path, const CacheKey &k, std::vector<char> &code)
+{
+    FILE *f = fopen(path.c_str(), "rb");
+    if (!f) return false;
+    char magic[8];
+    uint64_t hdr[3], n = 0;
+    bool ok = fread(magic, 1, 8, f) == 8 && !memcmp(magic, kCacheMagic, 8) && fread(hdr, 8, 3, f) == 3 &&
+              hdr[0] == k.h1 && hdr[1] == k.h2 && hdr[2] == k.len && fread(&n, 8, 1, f) == 1 && n > 0 &&
+              n < (1ull << 30);
+    if (ok) {
+        code.resize(n);
+        ok = fread(code.data(), 1, n, f) == n;
+    }
+    fclose(f);
+    return ok;
+}
+void cache_write(const std::string &path, const CacheKey &k, const std::vector<char> &code)
+{
+    const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+    FILE *f = fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    const uint64_t hdr[4] = {k.h1, k.h2, k.len, (uint64_t)code.size()};
+    bool ok = fwrite(kCacheMagic, 1, 8, f) == 8 && fwrite(hdr, 8, 4, f) == 4 &&
+              fwrite(code.data(), 1, code.size(), f) == code.size();
+    ok = (fclose(f) == 0) && ok;
+    if (!ok || rename(tmp.c_str(), path.c_str()) != 0) unlink(tmp.c_str());
+}
+
 std::string jit_source(const Plan &P, bool grad)
 {
     std::string s;
@@ -523,11 +615,28 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, do
     }
     auto t0 = std::chrono::steady_clock::now();
     std::string src = jit_source(P, grad);
+    std::string arch = "--offload-arch=" + D.arch;
+    const char *o[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    std::string keytext = src;
+    for (const char *opt : o) keytext += std::string("\n//") + opt;
+    const CacheKey ck = cache_key(keytext);
+    const std::string cdir = cache_dir();
+    std::vector<char> code;
+    if (!cdir.empty() && cache_read(cache_path(cdir, ck), ck, code)) {
+        JitEntry e;
+        if (hipModuleLoadData(&e.mod, code.data()) == hipSuccess &&
+            hipModuleGetFunction(&e.fn, e.mod, grad ? "bat_grad_jit" : "bat_fwd_jit") == hipSuccess) {
+            g_jit.emplace(key, e);
+            fn = e.fn;
+            compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            return BAT_OK;
+        }
+        if (e.mod) (void)hipModuleUnload(e.mod);
+        (void)hipGetLastError();  // a stale or damaged entry: compile afresh
+    }
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "bat_jit.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
         return fail(BAT_EDEVICE, "hiprtcCreateProgram failed");
-    std::string arch = "--offload-arch=" + D.arch;
-    const char *o[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
     hiprtcResult rc = hiprtcCompileProgram(prog, 7, o);
     if (rc != HIPRTC_SUCCESS) {
         size_t ls = 0;
@@ -539,9 +648,10 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, do
     }
     size_t sz = 0;
     hiprtcGetCodeSize(prog, &sz);
-    std::vector<char> code(sz);
+    code.assign(sz, 0);
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
+    if (!cdir.empty()) cache_write(cache_path(cdir, ck), ck, code);
     JitEntry e;
     HIPCHK(hipModuleLoadData(&e.mod, code.data()));
     HIPCHK(hipModuleGetFunction(&e.fn, e.mod, grad ? "bat_grad_jit" : "bat_fwd_jit"));
@@ -863,6 +973,10 @@ int bat_set_option(const char *key, int64_t value)
 {
     auto *o = opts().find(key);
     if (!o) return fail(BAT_EINVAL, "unknown option '%s'", key ? key : "(null)");
+    if (!strcmp(key, "BAT_JIT_FLUSH")) {  // an action, not a setting
+        if (value) jit_flush();
+        return BAT_OK;
+    }
     *o = value;
     return BAT_OK;
 }

@@ -469,6 +469,35 @@ def test_autotune_choice_keeps_results():
     assert g.count == c0 and rel_ok(g.R, R0)
 
 
+def test_jit_disk_cache(tmp_path, monkeypatch):
+    """Specialised kernels persist on disk: a compile writes one entry, a
+    flushed process loads it back with bit-identical results, an entry
+    whose header does not match is recompiled and rewritten, and
+    BAT_JIT_CACHE=0 writes nothing."""
+    B = _B()
+    monkeypatch.setenv("BAT_JIT_CACHE_DIR", str(tmp_path))
+    monkeypatch.delenv("BAT_JIT_CACHE", raising=False)
+    net = W.random_connected(11, 20, seed=515, p_lo=0.3, p_hi=0.95)
+    with options(BAT_JIT=1):
+        B.bat_set_option("BAT_JIT_FLUSH", 1)
+        R1, c1 = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+        assert B.bat_last_launch().specialised
+        files = sorted(tmp_path.glob("*.co"))
+        assert len(files) == 1 and files[0].stat().st_size > 1000
+        B.bat_set_option("BAT_JIT_FLUSH", 1)
+        R2, c2 = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+        assert (R2, c2) == (R1, c1) and sorted(tmp_path.glob("*.co")) == files
+        files[0].write_bytes(b"BATJIT1\n" + bytes(40))       # a header that matches nothing
+        B.bat_set_option("BAT_JIT_FLUSH", 1)
+        R3, c3 = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+        assert (R3, c3) == (R1, c1) and files[0].stat().st_size > 1000
+        monkeypatch.setenv("BAT_JIT_CACHE", "0")
+        other = W.random_connected(11, 21, seed=516, p_lo=0.3, p_hi=0.95)
+        B.bat_reliability(other.n, other.arcs, other.p, other.s, other.t)
+        assert sorted(tmp_path.glob("*.co")) == files
+    assert B.bat_get_option("BAT_JIT_FLUSH") == 0
+
+
 # ------------------------------------------------------- directed, forward
 
 def _digraph(seed, n, m):
