@@ -166,3 +166,26 @@ def test_flag_validation_without_device():
                                          ctypes.byref(lo), ctypes.byref(cnt), None, None)
     assert rc == -1 and "flags" in B.bat_last_error()
     assert B.BAT_DIRECTED == 1 and B.BAT_FORWARD_ORDER == 2
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/bat.h is a C header: a C99 translation unit that includes it
+    and takes the address of every declared function compiles warning-free."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = _declared()
+    src = ["#include \"bat.h\"", "#include <stddef.h>", "typedef void (*fp)(void);", "fp table[] = {"]
+    src += [f"    (fp){n}," for n in names]
+    src += ["};", "size_t n_table = sizeof table / sizeof table[0];",
+            "int check(void) { bat_arc a = {0, 1}; return a.u + a.v + BAT_OK + BAT_EINVAL + BAT_ETOOBIG"
+            " + BAT_EDEVICE + BAT_ENOMEM + BAT_MAX_NODES + BAT_MAX_ARCS + BAT_MAX_PVEC + (int)BAT_DIRECTED"
+            " + (int)BAT_FORWARD_ORDER; }"]
+    f = tmp_path / "abi.c"
+    f.write_text("\n".join(src) + "\n")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror",
+                        "-I", os.path.join(ROOT, "include"), "-c", str(f), "-o", str(tmp_path / "abi.o")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
