@@ -423,8 +423,19 @@ int current_device(DeviceInfo &D)
     return BAT_OK;
 }
 
+// Per thread and device: a device workspace and a pinned host staging
+// buffer the synchronous calls reuse (grown, never shrunk), so a small call
+// makes one host-to-device and one device-to-host copy and no allocation.
+struct Scratch {
+    char *dev = nullptr;
+    size_t dev_cap = 0;
+    char *host = nullptr;
+    size_t host_cap = 0;
+};
+
 struct ThreadState {
     std::map<int, hipStream_t> streams;
+    std::map<int, Scratch> scratch;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool have_launch = false;
     bat_launch_info info{};
@@ -445,6 +456,32 @@ int thread_stream(int dev, hipStream_t &s)
         it = t_state.streams.emplace(dev, st).first;
     }
     s = it->second;
+    return BAT_OK;
+}
+
+// Make the thread's scratch on device `dev` at least this large; growing
+// waits for the stream first (the old buffers may still be in use).
+int scratch_reserve(int dev, hipStream_t st, size_t dev_bytes, size_t host_bytes, Scratch *&S)
+{
+    S = &t_state.scratch[dev];
+    if (S->dev_cap < dev_bytes) {
+        HIPCHK(hipStreamSynchronize(st));
+        if (S->dev) HIPCHK(hipFree(S->dev));
+        S->dev = nullptr;
+        S->dev_cap = 0;
+        const size_t cap = std::max<size_t>(dev_bytes, 1 << 20);
+        HIPCHK(hipMalloc((void **)&S->dev, cap));
+        S->dev_cap = cap;
+    }
+    if (S->host_cap < host_bytes) {
+        HIPCHK(hipStreamSynchronize(st));
+        if (S->host) HIPCHK(hipHostFree(S->host));
+        S->host = nullptr;
+        S->host_cap = 0;
+        const size_t cap = std::max<size_t>(host_bytes, 64 << 10);
+        HIPCHK(hipHostMalloc((void **)&S->host, cap, hipHostMallocDefault));
+        S->host_cap = cap;
+    }
     return BAT_OK;
 }
 
@@ -719,20 +756,27 @@ TuneChoice choose(const DeviceInfo &D, const std::string &gkey, bool grad, const
 }
 
 struct Launch {
-    void *ws = nullptr;     // workspace (stream-ordered)
+    void *ws = nullptr;     // workspace (stream-ordered; null when the thread's scratch is used)
     double *res = nullptr;  // [ncol][2]
     u64 *count = nullptr;
     int *status = nullptr;
     const unsigned char *cb_of_arc = nullptr;
     u32 ncol = 1;
+    // the output block res | count | status, contiguous in the workspace,
+    // and where its host copy goes in the thread's staging buffer
+    const char *out_dev = nullptr;
+    size_t out_bytes = 0, out_host_off = 0;
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Queue tables + sweep + reduce on `stream`.  Allocates the workspace with
 // hipMallocAsync; the caller frees it on the same stream.
+// p_host (synchronous calls) is uploaded with the plan through the thread's
+// pinned staging buffer into its reused workspace; otherwise rq.p_dev is
+// already on the device and the workspace is allocated on the stream.
 int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const TuneChoice &tc, hipStream_t stream,
-                Launch &L)
+                Launch &L, const double *p_host = nullptr)
 {
     const u32 m = (u32)rq.m;
     const u32 ubits = m > (u32)bat::kWordBits ? m - bat::kWordBits : 0u;
@@ -802,27 +846,38 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     chain_codes(P, K.ck_code);
     L.ncol = K.ncol;
 
-    // workspace: tables | status | relax | rw | partials | counts | res | count
+    // workspace: input block (p | row, cb_of_arc maps | relaxation program),
+    // then tables | partials | counts | output block (res | count | status)
     size_t off = 0;
-    const size_t o_tab = off;
-    off = align_up(off + sizeof(double) * bat::kTables, 256);
-    const size_t o_st = off;
-    off = align_up(off + 64, 256);
+    const size_t o_p = off;
+    if (p_host) off = align_up(off + sizeof(double) * (m + 1), 256);
     const size_t o_map = off;  // row[64] | cb_of_arc[64]
     off = align_up(off + 128, 256);
     const size_t o_rl = off;
     off = align_up(off + sizeof(u32) * (P.prog.size() + 1), 256);
+    const size_t in_bytes = off;
+    const size_t o_tab = off;
+    off = align_up(off + sizeof(double) * bat::kTables, 256);
     const size_t o_part = off;
     off = align_up(off + sizeof(double) * 2 * K.ncol * K.n_chunks, 256);
     const size_t o_pc = off;
     off = align_up(off + sizeof(u64) * K.n_chunks, 256);
     const size_t o_res = off;
-    off = align_up(off + sizeof(double) * 2 * K.ncol, 256);
-    const size_t o_cnt = off;
-    off = align_up(off + sizeof(u64), 256);
+    const size_t o_cnt = o_res + sizeof(double) * 2 * K.ncol;
+    const size_t o_st = o_cnt + sizeof(u64);
+    const size_t out_bytes = o_st + sizeof(int) - o_res;
+    off = align_up(o_st + 64, 256);
     char *ws = nullptr;
-    HIPCHK(hipMallocAsync((void **)&ws, off, stream));
-    L.ws = ws;
+    Scratch *S = nullptr;
+    const size_t out_host_off = align_up(in_bytes, 256);
+    if (p_host) {
+        int rc = scratch_reserve(D.id, stream, off, out_host_off + out_bytes, S);
+        if (rc) return rc;
+        ws = S->dev;
+    } else {
+        HIPCHK(hipMallocAsync((void **)&ws, off, stream));
+        L.ws = ws;
+    }
     K.tables = (const double *)(ws + o_tab);
     K.status = (const int *)(ws + o_st);
     K.prog = (const u32 *)(ws + o_rl);
@@ -831,18 +886,32 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     L.res = (double *)(ws + o_res);
     L.count = (u64 *)(ws + o_cnt);
     L.status = (int *)(ws + o_st);
-    unsigned char maps[128];
-    memset(maps, 0, sizeof maps);
+    L.out_dev = ws + o_res;
+    L.out_bytes = out_bytes;
+    L.out_host_off = out_host_off;
+    // the input block, built once on the host and copied in one piece
+    std::vector<char> local;
+    char *in = nullptr;
+    if (S) {
+        in = S->host;
+    } else {
+        local.assign(in_bytes, 0);
+        in = local.data();
+    }
+    if (p_host && m > 0) memcpy(in + o_p, p_host, sizeof(double) * m);
+    unsigned char *maps = (unsigned char *)(in + o_map);
+    memset(maps, 0, 128);
     for (int i = 0; i < P.m; ++i) {
         maps[i] = P.row[i];
         maps[64 + i] = (unsigned char)P.cb_of_arc[i];
     }
-    HIPCHK(hipMemcpyAsync(ws + o_map, maps, sizeof maps, hipMemcpyHostToDevice, stream));
+    if (!P.prog.empty()) memcpy(in + o_rl, P.prog.data(), sizeof(u32) * P.prog.size());
+    HIPCHK(hipMemcpyAsync(ws, in, in_bytes, hipMemcpyHostToDevice, stream));
+    // (a copy from pageable memory has read its source when the call returns)
+    const double *p_dev = p_host ? (const double *)(ws + o_p) : rq.p_dev;
     const bool identity = P.identity;
     const unsigned char *d_row = identity ? nullptr : (const unsigned char *)(ws + o_map);
     L.cb_of_arc = identity ? nullptr : (const unsigned char *)(ws + o_map + 64);
-    if (!P.prog.empty())
-        HIPCHK(hipMemcpyAsync((void *)K.prog, P.prog.data(), sizeof(u32) * P.prog.size(), hipMemcpyHostToDevice, stream));
 
     hipFunction_t jfn = nullptr;
     double jit_ms = 0.0;
@@ -854,7 +923,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     int rc = events_ready();
     if (rc) return rc;
     HIPCHK(hipEventRecord(t_state.ev[0], stream));
-    HIPCHK(batk::build_tables(stream, rq.p_dev, d_row, m, f, (double *)K.tables, (int *)K.status));
+    HIPCHK(batk::build_tables(stream, p_dev, d_row, m, f, (double *)K.tables, (int *)K.status));
     HIPCHK(hipEventRecord(t_state.ev[1], stream));
     const u64 blocks = (K.n_chunks + bat::kWavesPerBlock - 1) / bat::kWavesPerBlock;
     if (blocks > 0x7fffffffull) return fail(BAT_ETOOBIG, "too many work items (%llu)", (unsigned long long)blocks);
@@ -921,28 +990,26 @@ int run_sync(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t
     if (rc) return rc;
     rc = thread_stream(X.D.id, X.stream);
     if (rc) return rc;
-    double *p_dev = nullptr;
-    HIPCHK(hipMallocAsync((void **)&p_dev, sizeof(double) * (m + 1), X.stream));
-    if (m > 0) HIPCHK(hipMemcpyAsync(p_dev, p, sizeof(double) * m, hipMemcpyHostToDevice, X.stream));
     Request rq = tmpl ? *tmpl : Request{};
-    rq.n = n; rq.m = m; rq.s = s; rq.t = t; rq.arcs = arcs; rq.p_dev = p_dev;
+    rq.n = n; rq.m = m; rq.s = s; rq.t = t; rq.arcs = arcs; rq.p_dev = nullptr;
     rq.c_lo = c_lo; rq.c_hi = c_hi; rq.grad = grad;
     Launch L;
-    rc = queue_sweep(rq, X.P, X.D, tc, X.stream, L);
+    static const double kNoArcs = 0.0;
+    rc = queue_sweep(rq, X.P, X.D, tc, X.stream, L, m > 0 ? p : &kNoArcs);
     if (rc) {
-        (void)hipFreeAsync(p_dev, X.stream);
-        if (L.ws) (void)hipFreeAsync(L.ws, X.stream);
         (void)hipStreamSynchronize(X.stream);
         return rc;
     }
-    res.assign(2 * L.ncol, 0.0);
-    int st = 0;
-    HIPCHK(hipMemcpyAsync(res.data(), L.res, sizeof(double) * 2 * L.ncol, hipMemcpyDeviceToHost, X.stream));
-    HIPCHK(hipMemcpyAsync(&count, L.count, sizeof(u64), hipMemcpyDeviceToHost, X.stream));
-    HIPCHK(hipMemcpyAsync(&st, L.status, sizeof(int), hipMemcpyDeviceToHost, X.stream));
-    HIPCHK(hipFreeAsync(L.ws, X.stream));
-    HIPCHK(hipFreeAsync(p_dev, X.stream));
+    // one copy back: res | count | status, into the pinned staging buffer
+    Scratch &S = t_state.scratch[X.D.id];
+    char *out = S.host + L.out_host_off;
+    HIPCHK(hipMemcpyAsync(out, L.out_dev, L.out_bytes, hipMemcpyDeviceToHost, X.stream));
     HIPCHK(hipStreamSynchronize(X.stream));
+    res.assign(2 * L.ncol, 0.0);
+    memcpy(res.data(), out, sizeof(double) * 2 * L.ncol);
+    memcpy(&count, out + sizeof(double) * 2 * L.ncol, sizeof(u64));
+    int st = 0;
+    memcpy(&st, out + sizeof(double) * 2 * L.ncol + sizeof(u64), sizeof(int));
     if (st) return fail(BAT_EINVAL, "a probability is outside [0,1]");
     if (cb_of_arc) *cb_of_arc = X.P.cb_of_arc;
     return BAT_OK;
