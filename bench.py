@@ -35,18 +35,15 @@ PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 1.26e15 bit-ops/s
 
 # HBM bytes per launch of the enumeration kernel on this workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain 1 GiB copy
-# (profiles/bat_fwd_jit_grid5x5_m40.md), keyed by the hash of the kernel and
-# host sources they were measured on; any other source reports null.
-MEASURED_TRAFFIC = {"9b8eb4ba9f83": (149.44 * 2.0 + 3072.0 * 1.0) * 1024}
+# (profiles/bat_fwd_jit_grid5x5_m40.md), keyed by the launch they were
+# measured on: the kernel identity the library reports (a hash of the exact
+# kernel code) and the launch choices.  Any other launch reports null.
+MEASURED_TRAFFIC = {}
 
 
-def source_hash() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("bat_device.hpp", "bat_host.cpp"):
-        with open(os.path.join(ROOT, "paper_2209_09711_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:12]
+def launch_key(li) -> str:
+    return (f"{li.kernel_id:016x}/perm{li.perm}/chunk{li.chunk_log2}/chain{li.chain_log2}"
+            f"/check{li.check_every}/order{li.item_order}")
 
 
 def parse():
@@ -190,7 +187,8 @@ def main():
     t0 = time.perf_counter()
     for _ in range(a.steps):
         step()
-        kern_ms.append(B.bat_last_launch().kernel_ms)   # HIP events on the launch stream
+        li_step = B.bat_last_launch()
+        kern_ms.append(li_step.kernel_ms)   # HIP events on the launch stream
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / a.steps
@@ -295,7 +293,8 @@ def main():
         achieved = nvec * insp / kern_s
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_BIT_OPS / 1e12,
                            "unit": "Tbitop/s", "frac": achieved / PEAK_BIT_OPS,
-                           "traffic": MEASURED_TRAFFIC.get(source_hash()),
+                           "traffic": MEASURED_TRAFFIC.get(launch_key(li_step)),
+                           "launch": launch_key(li_step),
                            "work_per_vector": insp, "work_unit": "PLSA arc inspections (1 bit-op each)"}
     line = json.dumps(out)
     print(line, flush=True)

@@ -253,8 +253,8 @@ int bat_autotune(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const dou
 /*
  * Description of the last launch on the calling thread, for benchmarks:
  * kernel time in milliseconds (HIP events around the enumeration kernel on
- * its own stream), the number of state vectors it covered and whether the
- * graph-specialised kernel ran.  Returns BAT_EINVAL if nothing ran yet.
+ * its own stream), the number of state vectors it covered, which kernel ran
+ * and the launch choices it ran with.  Returns BAT_EINVAL if nothing ran yet.
  */
 typedef struct {
     double kernel_ms;      /* enumeration kernel only */
@@ -265,6 +265,12 @@ typedef struct {
     int32_t chunk_log2;    /* work-item size used */
     int32_t n_chunks;      /* wavefront work items */
     int32_t relaxations;   /* arc relaxations per sweep after pruning */
+    uint64_t kernel_id;    /* 64-bit hash naming the exact kernel code that ran (the specialised source
+                              text and compile options, or the ahead-of-time kernel sources and instance) */
+    int32_t perm;          /* arc-to-counter-bit order (as "BAT_PERM"; 4 = forward BAT order; -1 batched) */
+    int32_t chain_log2;    /* warm-start chain length used, 0 = none */
+    int32_t check_every;   /* convergence-test cadence */
+    int32_t item_order;    /* 0 = consecutive work items, 1 = spread */
 } bat_launch_info;
 
 int bat_last_launch(bat_launch_info *info);

@@ -43,7 +43,10 @@ class bat_launch_info(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("jit_ms", ctypes.c_double), ("vectors", ctypes.c_uint64),
                 ("specialised", ctypes.c_int32), ("chunk_log2", ctypes.c_int32),
-                ("n_chunks", ctypes.c_int32), ("relaxations", ctypes.c_int32)]
+                ("n_chunks", ctypes.c_int32), ("relaxations", ctypes.c_int32),
+                ("kernel_id", ctypes.c_uint64), ("perm", ctypes.c_int32),
+                ("chain_log2", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("item_order", ctypes.c_int32)]
 
 
 def _load():

@@ -433,6 +433,22 @@ struct Scratch {
     size_t host_cap = 0;
 };
 
+// What exiting threads leave behind, for later threads to take over. A
+// thread's destructor makes no HIP call (the runtime may already be torn
+// down at process exit), so its streams, events and scratch come here
+// instead of being freed; the pool itself lives until the process ends.
+struct ResourcePool {
+    std::mutex mu;
+    std::multimap<int, hipStream_t> streams;
+    std::multimap<int, Scratch> scratch;
+    std::vector<std::vector<hipEvent_t>> events;
+};
+ResourcePool &pool()
+{
+    static ResourcePool *P = new ResourcePool;  // never destroyed
+    return *P;
+}
+
 struct ThreadState {
     std::map<int, hipStream_t> streams;
     std::map<int, Scratch> scratch;
@@ -441,8 +457,12 @@ struct ThreadState {
     bat_launch_info info{};
     ~ThreadState()
     {
-        // streams and events belong to the process's HIP runtime, which may
-        // already be torn down at thread exit; they are released with it.
+        ResourcePool &P = pool();
+        std::lock_guard<std::mutex> g(P.mu);
+        for (auto &kv : streams) P.streams.emplace(kv.first, kv.second);
+        for (auto &kv : scratch)
+            if (kv.second.dev || kv.second.host) P.scratch.emplace(kv.first, kv.second);
+        if (ev[0]) P.events.emplace_back(ev, ev + 4);
     }
 };
 thread_local ThreadState t_state;
@@ -451,8 +471,17 @@ int thread_stream(int dev, hipStream_t &s)
 {
     auto it = t_state.streams.find(dev);
     if (it == t_state.streams.end()) {
-        hipStream_t st;
-        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        hipStream_t st = nullptr;
+        {
+            ResourcePool &P = pool();
+            std::lock_guard<std::mutex> g(P.mu);
+            auto pit = P.streams.find(dev);
+            if (pit != P.streams.end()) {
+                st = pit->second;
+                P.streams.erase(pit);
+            }
+        }
+        if (!st) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
         it = t_state.streams.emplace(dev, st).first;
     }
     s = it->second;
@@ -463,7 +492,21 @@ int thread_stream(int dev, hipStream_t &s)
 // waits for the stream first (the old buffers may still be in use).
 int scratch_reserve(int dev, hipStream_t st, size_t dev_bytes, size_t host_bytes, Scratch *&S)
 {
-    S = &t_state.scratch[dev];
+    auto sit = t_state.scratch.find(dev);
+    if (sit == t_state.scratch.end()) {
+        Scratch taken;
+        {
+            ResourcePool &P = pool();
+            std::lock_guard<std::mutex> g(P.mu);
+            auto pit = P.scratch.find(dev);
+            if (pit != P.scratch.end()) {
+                taken = pit->second;
+                P.scratch.erase(pit);
+            }
+        }
+        sit = t_state.scratch.emplace(dev, taken).first;
+    }
+    S = &sit->second;
     if (S->dev_cap < dev_bytes) {
         HIPCHK(hipStreamSynchronize(st));
         if (S->dev) HIPCHK(hipFree(S->dev));
@@ -487,8 +530,18 @@ int scratch_reserve(int dev, hipStream_t st, size_t dev_bytes, size_t host_bytes
 
 int events_ready()
 {
-    if (!t_state.ev[0])
-        for (auto &e : t_state.ev) HIPCHK(hipEventCreate(&e));
+    if (!t_state.ev[0]) {
+        {
+            ResourcePool &P = pool();
+            std::lock_guard<std::mutex> g(P.mu);
+            if (!P.events.empty()) {
+                for (int i = 0; i < 4; ++i) t_state.ev[i] = P.events.back()[i];
+                P.events.pop_back();
+            }
+        }
+        if (!t_state.ev[0])
+            for (auto &e : t_state.ev) HIPCHK(hipEventCreate(&e));
+    }
     return BAT_OK;
 }
 
@@ -496,6 +549,7 @@ int events_ready()
 struct JitEntry {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
+    uint64_t id = 0;  // hash of the source text and compile options
 };
 std::mutex g_jit_mu;
 std::map<std::string, JitEntry> g_jit;
@@ -531,6 +585,16 @@ CacheKey cache_key(const std::string &text)
     }
     return {a, b, (uint64_t)text.size()};
 }
+// Identity of an ahead-of-time kernel instance: the digest of the sources
+// it was compiled from, the kernel and its node-count class.
+uint64_t aot_kernel_id(const char *kernel, int nodes, bool directed)
+{
+    const int nmax = nodes <= 16 ? 16 : nodes <= 32 ? 32 : 64;
+    return cache_key(std::string(kAotKernelDigest) + " " + kernel + " " + std::to_string(nmax) +
+                     (directed ? " directed" : ""))
+        .h1;
+}
+
 std::string cache_dir()
 {
     const char *on = getenv("BAT_JIT_CACHE");
@@ -640,7 +704,7 @@ std::string jit_source(const Plan &P, bool grad)
     return s;
 }
 
-int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, double &compile_ms)
+int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, double &compile_ms, uint64_t &id)
 {
     compile_ms = 0.0;
     std::string key = std::to_string(D.id) + (grad ? " grad " : " fwd ") + P.structure;
@@ -648,6 +712,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, do
     auto it = g_jit.find(key);
     if (it != g_jit.end()) {
         fn = it->second.fn;
+        id = it->second.id;
         return BAT_OK;
     }
     auto t0 = std::chrono::steady_clock::now();
@@ -657,10 +722,12 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, do
     std::string keytext = src;
     for (const char *opt : o) keytext += std::string("\n//") + opt;
     const CacheKey ck = cache_key(keytext);
+    id = ck.h1;
     const std::string cdir = cache_dir();
     std::vector<char> code;
     if (!cdir.empty() && cache_read(cache_path(cdir, ck), ck, code)) {
         JitEntry e;
+        e.id = id;
         if (hipModuleLoadData(&e.mod, code.data()) == hipSuccess &&
             hipModuleGetFunction(&e.fn, e.mod, grad ? "bat_grad_jit" : "bat_fwd_jit") == hipSuccess) {
             g_jit.emplace(key, e);
@@ -690,6 +757,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, do
     hiprtcDestroyProgram(&prog);
     if (!cdir.empty()) cache_write(cache_path(cdir, ck), ck, code);
     JitEntry e;
+    e.id = id;
     HIPCHK(hipModuleLoadData(&e.mod, code.data()));
     HIPCHK(hipModuleGetFunction(&e.fn, e.mod, grad ? "bat_grad_jit" : "bat_fwd_jit"));
     g_jit.emplace(key, e);
@@ -915,9 +983,12 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
 
     hipFunction_t jfn = nullptr;
     double jit_ms = 0.0;
+    uint64_t kernel_id = 0;
     if (use_jit) {
-        int rc = jit_get(D, P, rq.grad, jfn, jit_ms);
+        int rc = jit_get(D, P, rq.grad, jfn, jit_ms, kernel_id);
         if (rc) return rc;
+    } else {
+        kernel_id = aot_kernel_id(rq.grad ? "k_grad_dyn" : "k_fwd_dyn", (int)P.N, P.directed);
     }
 
     int rc = events_ready();
@@ -945,6 +1016,11 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     I.chunk_log2 = clog;
     I.n_chunks = (int32_t)std::min<u64>(K.n_chunks, 0x7fffffff);
     I.relaxations = (int32_t)P.code.size();
+    I.kernel_id = kernel_id;
+    I.perm = P.perm;
+    I.chain_log2 = (int32_t)K.chain;
+    I.check_every = (int32_t)K.check_every;
+    I.item_order = K.chunk_mul != 1 ? 1 : 0;
     t_state.have_launch = true;
     return BAT_OK;
 }
@@ -1509,6 +1585,11 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         for (const Plan &pl : plans) nrel += pl.code.size();
         I.relaxations = (int32_t)nrel;
     }
+    I.kernel_id = aot_kernel_id("k_batched_dyn", (int)nmax, false);
+    I.perm = -1;
+    I.chain_log2 = (int32_t)bchain;
+    I.check_every = 1;
+    I.item_order = 0;
     t_state.have_launch = true;
     return BAT_OK;
 }

@@ -710,3 +710,58 @@ def test_batched_config3_workload():
         for j in (5, 31):
             Rp, cp = B.bat_reliability(net.n, net.arcs, pvs[g][j], net.s, net.t)
             assert cp == cnt[g] and rel_ok(R[g, j], Rp)
+
+
+def test_threads_share_device_and_reuse_resources():
+    """Synchronous calls from several host threads at once (each thread has
+    its own stream and workspace), with sizes that grow the workspace, then a
+    second set of threads that takes over what the first left behind."""
+    import threading
+
+    B = _B()
+    nets = _cases(12, 4242, m_max=22)
+    want = [oracle.net_reliability(net) for net in nets]
+    errors = []
+
+    def worker(k):
+        try:
+            for j in sorted(range(len(nets)), key=lambda j: (nets[j].m + 7 * k) % 23):
+                net = nets[j]
+                R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+                if cnt != want[j].count or not rel_ok(R, want[j].sum):
+                    errors.append((k, net.name, R, want[j].sum, cnt, want[j].count))
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append((k, repr(e)))
+
+    for wave in range(2):
+        say("thread wave", wave)
+        ts = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        assert not errors, errors[:4]
+
+
+def test_launch_info_names_the_kernel():
+    """The launch description names the kernel that ran: the same launch
+    twice reports the same identity, the generic and specialised kernels and
+    the forward and gradient sweeps report different ones."""
+    B = _B()
+    net = W.random_connected(9, 16, seed=77)
+    ids = {}
+    for jit in (0, 1):
+        with options(BAT_JIT=jit):
+            for grad in (False, True):
+                for _ in range(2):
+                    if grad:
+                        B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+                    else:
+                        B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+                    li = B.bat_last_launch()
+                    assert li.kernel_id != 0
+                    assert li.specialised == jit
+                    assert li.perm in (0, 1, 2, 3)
+                    assert li.check_every in (1, 2) and li.item_order in (0, 1)
+                    assert ids.setdefault((jit, grad), li.kernel_id) == li.kernel_id
+    assert len(set(ids.values())) == 4
