@@ -68,7 +68,7 @@ int fail(int code, const char *fmt, ...)
 // ------------------------------------------------------------ options
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
-        jit_flush_req{0};
+        window_test{1}, jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -83,6 +83,7 @@ struct Options {
         rd("BAT_PERM", perm);
         rd("BAT_CHAIN_LOG2", chain_log2);
         rd("BAT_ITEM_ORDER", item_order);
+        rd("BAT_WINDOW_TEST", window_test);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -95,6 +96,7 @@ struct Options {
         if (!strcmp(k, "BAT_PERM")) return &perm;
         if (!strcmp(k, "BAT_CHAIN_LOG2")) return &chain_log2;
         if (!strcmp(k, "BAT_ITEM_ORDER")) return &item_order;
+        if (!strcmp(k, "BAT_WINDOW_TEST")) return &window_test;
         if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
@@ -906,6 +908,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     K.check_every = tc.check_every >= 2 ? 2u : 1u;
     K.chain = chain ? ck : 0u;
     K.ncol = rq.grad ? 1u + 2u * m : 1u;
+    K.window_test = (chain && !rq.grad && O.window_test.load() != 0) ? 1u : 0u;
     K.n_nodes = (u32)P.N;
     K.s = (u32)P.S;
     K.t = (u32)P.T;
