@@ -33,17 +33,21 @@ CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_LANE_OPS = CUS * LANES * CLOCK_HZ            # 3.93e13 int32 lane-ops/s
 PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 1.26e15 bit-ops/s
 
-# HBM bytes per launch of the enumeration kernel on this workload, from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain 1 GiB copy
+# Hardware counters of the enumeration kernel on this workload
 # (profiles/bat_fwd_jit_grid5x5_m40.md), keyed by the launch they were
 # measured on: the kernel identity the library reports (a hash of the exact
 # kernel code) and the launch choices.  Any other launch reports null.
-MEASURED_TRAFFIC = {}
+#   traffic_bytes: HBM bytes per launch, rocprofv3 FETCH_SIZE x 2.0 +
+#     WRITE_SIZE x 1.0 (KiB), the factors of a plain 1 GiB device copy;
+#   valu_busy: SQ_INSTS_VALU / (256 CUs x GRBM_GUI_ACTIVE cycles);
+#   valu_insts_per_vector: SQ_INSTS_VALU x 64 lanes / 2^40 (lane-ops).
+MEASURED = {}
 
 
 def launch_key(li) -> str:
     return (f"{li.kernel_id:016x}/perm{li.perm}/chunk{li.chunk_log2}/chain{li.chain_log2}"
-            f"/check{li.check_every}/order{li.item_order}")
+            f"/check{li.check_every}/order{li.item_order}/waves{li.block_waves}/super{li.super_restart}"
+            f"/window{li.window_test}")
 
 
 def parse():
@@ -293,7 +297,9 @@ def main():
         achieved = nvec * insp / kern_s
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_BIT_OPS / 1e12,
                            "unit": "Tbitop/s", "frac": achieved / PEAK_BIT_OPS,
-                           "traffic": MEASURED_TRAFFIC.get(launch_key(li_step)),
+                           "traffic": MEASURED.get(launch_key(li_step), {}).get("traffic_bytes"),
+                           "valu_busy": MEASURED.get(launch_key(li_step), {}).get("valu_busy"),
+                           "valu_insts_per_vector": MEASURED.get(launch_key(li_step), {}).get("valu_insts_per_vector"),
                            "launch": launch_key(li_step),
                            "work_per_vector": insp, "work_unit": "PLSA arc inspections (1 bit-op each)"}
     line = json.dumps(out)

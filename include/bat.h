@@ -221,6 +221,19 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
  *                      cover distant parts of the counter), 0 = counter
  *                      order; R and counts never depend on it beyond
  *                      floating-point rounding
+ *   "BAT_WINDOW_TEST"  1 (default) = the graph-specialised forward sweep
+ *                      tests each window of 2048 iterations once, with all
+ *                      11 word arcs up, and skips the chained blocks whose
+ *                      last iteration cannot connect s and t (none of their
+ *                      vectors can); 0 = sweep every block.  Results are
+ *                      identical either way
+ *   "BAT_BLOCK_WAVES"  wavefronts per block of the graph-specialised
+ *                      forward sweep: -1 = tuned (else 4), 1, 2 or 4
+ *   "BAT_SUPER_RESTART" graph-specialised forward sweeps of graphs of up to
+ *                      28 relevant nodes: 1 = keep each 64-iteration
+ *                      super-block's bottom closure in LDS and resume later
+ *                      block bottoms from it, 0 = solve block bottoms
+ *                      afresh, -1 = tuned (else 0)
  *   "BAT_JIT_FLUSH"    setting it to a nonzero value unloads every
  *                      graph-specialised kernel this process compiled or
  *                      loaded (after the current device finishes its work;
@@ -271,6 +284,10 @@ typedef struct {
     int32_t chain_log2;    /* warm-start chain length used, 0 = none */
     int32_t check_every;   /* convergence-test cadence */
     int32_t item_order;    /* 0 = consecutive work items, 1 = spread */
+    int32_t block_waves;   /* wavefronts per block */
+    int32_t super_restart; /* 1 if block bottoms resume from a kept super-block bottom */
+    int32_t window_test;   /* 1 if chained blocks that cannot connect s and t were skipped */
+    int32_t reserved;
 } bat_launch_info;
 
 int bat_last_launch(bat_launch_info *info);

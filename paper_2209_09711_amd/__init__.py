@@ -46,7 +46,9 @@ class bat_launch_info(ctypes.Structure):
                 ("n_chunks", ctypes.c_int32), ("relaxations", ctypes.c_int32),
                 ("kernel_id", ctypes.c_uint64), ("perm", ctypes.c_int32),
                 ("chain_log2", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("item_order", ctypes.c_int32)]
+                ("item_order", ctypes.c_int32), ("block_waves", ctypes.c_int32),
+                ("super_restart", ctypes.c_int32), ("window_test", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 def _load():

@@ -68,7 +68,7 @@ int fail(int code, const char *fmt, ...)
 // ------------------------------------------------------------ options
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
-        window_test{1}, jit_flush_req{0};
+        window_test{1}, block_waves{-1}, super_restart{-1}, jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -84,6 +84,8 @@ struct Options {
         rd("BAT_CHAIN_LOG2", chain_log2);
         rd("BAT_ITEM_ORDER", item_order);
         rd("BAT_WINDOW_TEST", window_test);
+        rd("BAT_BLOCK_WAVES", block_waves);
+        rd("BAT_SUPER_RESTART", super_restart);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -97,6 +99,8 @@ struct Options {
         if (!strcmp(k, "BAT_CHAIN_LOG2")) return &chain_log2;
         if (!strcmp(k, "BAT_ITEM_ORDER")) return &item_order;
         if (!strcmp(k, "BAT_WINDOW_TEST")) return &window_test;
+        if (!strcmp(k, "BAT_BLOCK_WAVES")) return &block_waves;
+        if (!strcmp(k, "BAT_SUPER_RESTART")) return &super_restart;
         if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
@@ -653,7 +657,26 @@ void cache_write(const std::string &path, const CacheKey &k, const std::vector<c
     if (!ok || rename(tmp.c_str(), path.c_str()) != 0) unlink(tmp.c_str());
 }
 
-std::string jit_source(const Plan &P, bool grad)
+// Launch shape of a specialised kernel: wavefronts per block and whether
+// forward sweeps keep super-block bottoms in LDS.  The gradient sweep
+// always runs 4 wavefronts per block and no super-block store.
+struct JitShape {
+    int waves = bat::kWavesPerBlock;
+    bool super_restart = false;
+};
+
+// waves: 1, 2 or 4 (anything else: 4); super_restart: 1 on, else off
+JitShape jit_shape(bool grad, int waves, int super_restart)
+{
+    JitShape sh;
+    if (!grad) {
+        sh.waves = waves == 1 ? 1 : waves == 2 ? 2 : 4;
+        sh.super_restart = super_restart == 1;
+    }
+    return sh;
+}
+
+std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
 {
     std::string s;
     s.reserve(strlen(kDeviceSource) + 4096);
@@ -678,7 +701,10 @@ std::string jit_source(const Plan &P, bool grad)
     // forward sweeps of graphs small enough for the LDS store (4 blocks of
     // 4 wavefronts per CU keep (N + 2) words per lane each) also resume
     // block bottoms from the kept bottom of their 2^6-aligned super-block
-    s += std::string("  static constexpr bool SUPER = ") + (!grad && P.N <= kSuperMaxNodes ? "true" : "false") + ";\n";
+    s += std::string("  static constexpr bool SUPER = ") +
+         (!grad && sh.super_restart && P.N <= kSuperMaxNodes ? "true" : "false") + ";\n";
+    // wavefronts per block (the launch uses the same)
+    s += "  static constexpr int WAVES = " + std::to_string(sh.waves) + ";\n";
     // relaxations of counter bits 11..16 (the chained iteration arcs)
     int ck[6] = {-1, -1, -1, -1, -1, -1};
     for (size_t k = 0; k < nr; ++k)
@@ -700,16 +726,19 @@ std::string jit_source(const Plan &P, bool grad)
              "  __shared__ bat::LdsTables L; __shared__ bat::LdsGrad LG;\n"
              "  bat::sweep_kernel<bat::StaticClosure<JitGraph, false>, true>(P, L, &LG);\n}\n";
     else
-        s += "extern \"C\" __global__ void __launch_bounds__(256) bat_fwd_jit(bat::KParams P) {\n"
+        s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(bat::kWave * sh.waves) +
+             ") bat_fwd_jit(bat::KParams P) {\n"
              "  __shared__ bat::LdsTables L;\n"
              "  bat::sweep_kernel<bat::StaticClosure<JitGraph>, false>(P, L, nullptr);\n}\n";
     return s;
 }
 
-int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, double &compile_ms, uint64_t &id)
+int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, hipFunction_t &fn, double &compile_ms,
+            uint64_t &id)
 {
     compile_ms = 0.0;
-    std::string key = std::to_string(D.id) + (grad ? " grad " : " fwd ") + P.structure;
+    std::string key = std::to_string(D.id) + (grad ? " grad " : " fwd ") + std::to_string(sh.waves) +
+                      (sh.super_restart ? "s " : " ") + P.structure;
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto it = g_jit.find(key);
     if (it != g_jit.end()) {
@@ -718,7 +747,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, do
         return BAT_OK;
     }
     auto t0 = std::chrono::steady_clock::now();
-    std::string src = jit_source(P, grad);
+    std::string src = jit_source(P, grad, sh);
     std::string arch = "--offload-arch=" + D.arch;
     const char *o[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
     std::string keytext = src;
@@ -771,6 +800,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, hipFunction_t &fn, do
 // ------------------------------------------------------------ autotune cache
 struct TuneChoice {
     int chunk_log2, check_every, jit, perm, chain = -1, order = -1;
+    int waves = -1, super_restart = -1;  // specialised forward launch shape (-1: default)
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneChoice> g_tune;
@@ -794,7 +824,7 @@ struct Request {
     bool grad;
     // forced knobs (autotuner); -1 = from options / the tuned choice
     int force_chunk_log2 = -1, force_check = -1, force_jit = -1, force_perm = -1, force_chain = -1,
-        force_order = -1;
+        force_order = -1, force_waves = -1, force_super = -1;
     // timing sample (autotuner): sweep only this many work items, spread
     // over the whole counter by an odd multiplier (0 = everything)
     u64 sample_items = 0;
@@ -814,6 +844,8 @@ TuneChoice choose(const DeviceInfo &D, const std::string &gkey, bool grad, const
     if (O.perm.load() >= 0) tc.perm = (int)O.perm.load();
     if (O.chain_log2.load() >= 0) tc.chain = (int)O.chain_log2.load();
     if (O.item_order.load() >= 0) tc.order = (int)O.item_order.load();
+    if (O.block_waves.load() >= 0) tc.waves = (int)O.block_waves.load();
+    if (O.super_restart.load() >= 0) tc.super_restart = (int)O.super_restart.load();
     if (rq) {
         if (rq->force_chunk_log2 >= 0) tc.chunk_log2 = rq->force_chunk_log2;
         if (rq->force_check >= 0) tc.check_every = rq->force_check;
@@ -821,6 +853,8 @@ TuneChoice choose(const DeviceInfo &D, const std::string &gkey, bool grad, const
         if (rq->force_perm >= 0) tc.perm = rq->force_perm;
         if (rq->force_chain >= 0) tc.chain = rq->force_chain;
         if (rq->force_order >= 0) tc.order = rq->force_order;
+        if (rq->force_waves >= 0) tc.waves = rq->force_waves;
+        if (rq->force_super >= 0) tc.super_restart = rq->force_super;
     }
     return tc;
 }
@@ -987,8 +1021,9 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     hipFunction_t jfn = nullptr;
     double jit_ms = 0.0;
     uint64_t kernel_id = 0;
+    const JitShape shape = jit_shape(rq.grad, tc.waves, tc.super_restart);
     if (use_jit) {
-        int rc = jit_get(D, P, rq.grad, jfn, jit_ms, kernel_id);
+        int rc = jit_get(D, P, rq.grad, shape, jfn, jit_ms, kernel_id);
         if (rc) return rc;
     } else {
         kernel_id = aot_kernel_id(rq.grad ? "k_grad_dyn" : "k_fwd_dyn", (int)P.N, P.directed);
@@ -999,11 +1034,14 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     HIPCHK(hipEventRecord(t_state.ev[0], stream));
     HIPCHK(batk::build_tables(stream, p_dev, d_row, m, f, (double *)K.tables, (int *)K.status));
     HIPCHK(hipEventRecord(t_state.ev[1], stream));
-    const u64 blocks = (K.n_chunks + bat::kWavesPerBlock - 1) / bat::kWavesPerBlock;
+    // one work item per wavefront
+    const u64 wpb = use_jit ? (u64)shape.waves : (u64)bat::kWavesPerBlock;
+    const u64 blocks = (K.n_chunks + wpb - 1) / wpb;
     if (blocks > 0x7fffffffull) return fail(BAT_ETOOBIG, "too many work items (%llu)", (unsigned long long)blocks);
     if (use_jit) {
         void *args[] = {&K};
-        HIPCHK(hipModuleLaunchKernel(jfn, (unsigned)blocks, 1, 1, bat::kBlock, 1, 1, 0, stream, args, nullptr));
+        HIPCHK(hipModuleLaunchKernel(jfn, (unsigned)blocks, 1, 1, (unsigned)(bat::kWave * wpb), 1, 1, 0, stream, args,
+                                     nullptr));
     } else {
         HIPCHK(batk::sweep_dyn(stream, (unsigned)blocks, rq.grad, P.N, P.directed, K));
     }
@@ -1024,6 +1062,9 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     I.chain_log2 = (int32_t)K.chain;
     I.check_every = (int32_t)K.check_every;
     I.item_order = K.chunk_mul != 1 ? 1 : 0;
+    I.block_waves = (int32_t)wpb;
+    I.super_restart = (use_jit && shape.super_restart && P.N <= kSuperMaxNodes) ? 1 : 0;
+    I.window_test = (int32_t)K.window_test;
     t_state.have_launch = true;
     return BAT_OK;
 }
@@ -1283,7 +1324,9 @@ int bat_jit_source(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t
     if (perm < 0 || perm >= kPermKinds) return fail(BAT_EINVAL, "perm %d outside [0, %d)", perm, kPermKinds);
     Plan P;
     make_plan(n, m, arcs, s, t, P, perm, (flags & BAT_DIRECTED) != 0);
-    const std::string src = jit_source(P, grad != 0);
+    Options &O = opts();
+    const std::string src =
+        jit_source(P, grad != 0, jit_shape(grad != 0, (int)O.block_waves.load(), (int)O.super_restart.load()));
     const uint64_t need = (uint64_t)src.size() + 1;
     const uint64_t have = *len;
     *len = need;
@@ -1317,7 +1360,8 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         u64 target = (1ull << ubits) / ((u64)std::max(D.cus, 1) * 64ull);
         while (clog_auto < 12 && (2ull << clog_auto) <= target) ++clog_auto;
     }
-    struct Cand { int clog, check, jit, perm, chain; };
+    struct Cand { int clog, check, jit, perm, chain, waves = -1, super_restart = -1; };
+    constexpr double kTuneMargin = 0.01;
     auto measure = [&](const Cand &c, double &ns) -> bool {
         ns = 1e300;
         for (int rep = 0; rep < 3; ++rep) {  // the first pass warms the JIT cache
@@ -1327,6 +1371,8 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
             tmpl.force_jit = c.jit;
             tmpl.force_perm = c.perm;
             tmpl.force_chain = c.chain;
+            tmpl.force_waves = c.waves;
+            tmpl.force_super = c.super_restart;
             const int cl = c.clog > 0 ? c.clog : std::max(clog_auto, 3);
             const u64 per_item = 1ull << (cl + bat::kWordBits);
             tmpl.sample_items = std::max<u64>(1024, (1ull << 38) / per_item);
@@ -1346,17 +1392,24 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         double ns;
         const bool ok = measure(c, ns);
         if (verbose)
-            fprintf(stderr, "bat_autotune: chunk_log2=%d check=%d jit=%d perm=%d chain=%d -> %s %.6f ns/vector\n",
-                    c.clog, c.check, c.jit, c.perm, c.chain, ok ? "ok" : "failed", ok ? ns : 0.0);
-        if (ok && ns < best) {
+            fprintf(stderr,
+                    "bat_autotune: chunk_log2=%d check=%d jit=%d perm=%d chain=%d waves=%d super=%d -> %s %.6f "
+                    "ns/vector\n",
+                    c.clog, c.check, c.jit, c.perm, c.chain, c.waves, c.super_restart, ok ? "ok" : "failed",
+                    ok ? ns : 0.0);
+        // a later candidate must win by a margin: near ties keep the
+        // earlier (default-first) choice, so repeated tuning agrees
+        if (ok && ns < best * (1.0 - kTuneMargin)) {
             best = ns;
             bc = c;
         }
     };
     // stage 1: arc-to-bit order x chain length, specialised kernel,
-    // automatic work-item size (the two interact)
-    for (int perm = 0; perm < kPermKinds; ++perm)
+    // automatic work-item size (the two interact); the default order first
+    for (int i = 0; i < kPermKinds; ++i) {
+        const int perm = (kDefaultPerm + i) % kPermKinds;
         for (int k : {3, 5}) consider({0, 1, 1, perm, k});
+    }
     {
         const Cand w1 = bc;
         for (int k : {4, 6})
@@ -1369,12 +1422,23 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         if (cl >= 5 && cl <= 14) consider({cl, w.check, w.jit, w.perm, w.chain});
     }
     consider({bc.clog, 2, bc.jit, bc.perm, bc.chain});
+    // launch shape of the specialised forward sweep: blocks of 2 wavefronts
+    // and the super-block store (which takes LDS, so whole 4-wavefront
+    // blocks wait for it)
+    if (bc.jit != 0) {
+        const Cand w2 = bc;
+        consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, 4, 1});
+        consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, 2, 0});
+        consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, 2, 1});
+    }
     if (total <= (1ull << 32)) consider({bc.clog, 1, 0, 0, 0});
     if (best >= 1e300) return fail(BAT_EDEVICE, "autotune: no candidate ran (%s)", t_err.c_str());
     if (best_ns_per_vector) *best_ns_per_vector = best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         TuneChoice tc{bc.clog, bc.check, bc.jit, bc.perm, bc.chain};
+        tc.waves = bc.waves;
+        tc.super_restart = bc.super_restart;
         const std::string gk = graph_key(n, m, arcs, s, t);
         g_tune[std::to_string(D.id) + " fwd " + gk] = tc;
         g_tune[std::to_string(D.id) + " grad " + gk] = tc;
@@ -1593,6 +1657,9 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     I.chain_log2 = (int32_t)bchain;
     I.check_every = 1;
     I.item_order = 0;
+    I.block_waves = (int32_t)batk::batch_waves(nmax);
+    I.super_restart = 0;
+    I.window_test = 0;
     t_state.have_launch = true;
     return BAT_OK;
 }
