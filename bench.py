@@ -47,7 +47,7 @@ MEASURED = {}
 def launch_key(li) -> str:
     return (f"{li.kernel_id:016x}/perm{li.perm}/chunk{li.chunk_log2}/chain{li.chain_log2}"
             f"/check{li.check_every}/order{li.item_order}/waves{li.block_waves}/super{li.super_restart}"
-            f"/window{li.window_test}")
+            f"/window{li.window_test}/simd{li.simd_waves}/keep{li.keep_bottom}")
 
 
 def parse():

@@ -234,6 +234,14 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
  *                      super-block's bottom closure in LDS and resume later
  *                      block bottoms from it, 0 = solve block bottoms
  *                      afresh, -1 = tuned (else 0)
+ *   "BAT_SIMD_WAVES"   graph-specialised forward sweep: compile it to fit
+ *                      this many wavefronts per SIMD (5..8; the compiler
+ *                      then keeps fewer registers and may spill), 0 = the
+ *                      compiler's own budget, -1 = tuned (else 6)
+ *   "BAT_KEEP_BOTTOM"  graph-specialised forward sweep: 1 = keep each
+ *                      chained block's bottom closure in registers and
+ *                      resume later chain starts from it, 0 = solve chain
+ *                      starts afresh, -1 = tuned (else 1)
  *   "BAT_JIT_FLUSH"    setting it to a nonzero value unloads every
  *                      graph-specialised kernel this process compiled or
  *                      loaded (after the current device finishes its work;
@@ -287,6 +295,8 @@ typedef struct {
     int32_t block_waves;   /* wavefronts per block */
     int32_t super_restart; /* 1 if block bottoms resume from a kept super-block bottom */
     int32_t window_test;   /* 1 if chained blocks that cannot connect s and t were skipped */
+    int32_t simd_waves;    /* wavefronts per SIMD the kernel was compiled to fit, 0 = compiler's choice */
+    int32_t keep_bottom;   /* 1 if chain starts resumed from the block bottom kept in registers */
     int32_t reserved;
 } bat_launch_info;
 

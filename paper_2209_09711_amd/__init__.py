@@ -48,6 +48,7 @@ class bat_launch_info(ctypes.Structure):
                 ("chain_log2", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("item_order", ctypes.c_int32), ("block_waves", ctypes.c_int32),
                 ("super_restart", ctypes.c_int32), ("window_test", ctypes.c_int32),
+                ("simd_waves", ctypes.c_int32), ("keep_bottom", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 

@@ -68,7 +68,7 @@ int fail(int code, const char *fmt, ...)
 // ------------------------------------------------------------ options
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
-        window_test{1}, block_waves{-1}, super_restart{-1}, jit_flush_req{0};
+        window_test{1}, block_waves{-1}, super_restart{-1}, simd_waves{-1}, keep_bottom{-1}, jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -86,6 +86,8 @@ struct Options {
         rd("BAT_WINDOW_TEST", window_test);
         rd("BAT_BLOCK_WAVES", block_waves);
         rd("BAT_SUPER_RESTART", super_restart);
+        rd("BAT_SIMD_WAVES", simd_waves);
+        rd("BAT_KEEP_BOTTOM", keep_bottom);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -101,6 +103,8 @@ struct Options {
         if (!strcmp(k, "BAT_WINDOW_TEST")) return &window_test;
         if (!strcmp(k, "BAT_BLOCK_WAVES")) return &block_waves;
         if (!strcmp(k, "BAT_SUPER_RESTART")) return &super_restart;
+        if (!strcmp(k, "BAT_SIMD_WAVES")) return &simd_waves;
+        if (!strcmp(k, "BAT_KEEP_BOTTOM")) return &keep_bottom;
         if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
@@ -663,15 +667,28 @@ void cache_write(const std::string &path, const CacheKey &k, const std::vector<c
 struct JitShape {
     int waves = bat::kWavesPerBlock;
     bool super_restart = false;
+    int simd_waves = 0;  // > 0: ask the compiler to fit this many wavefronts per SIMD
+    bool keep_bottom = true;  // chain starts resume from the block bottom kept in registers
 };
 
-// waves: 1, 2 or 4 (anything else: 4); super_restart: 1 on, else off
-JitShape jit_shape(bool grad, int waves, int super_restart)
+// Default shape of the forward sweep: 4 wavefronts per block, kept block
+// bottoms, no super-block store, compiled to fit 6 wavefronts per SIMD.
+// The kernel is latency-bound: on the 5x5 grid, fitting 6 wavefronts (80
+// registers, a few spills outside the innermost loops) instead of the
+// compiler's 4 (109 registers) takes the sweep from 161 to 141 ms.
+constexpr int kDefaultSimdWaves = 6;
+
+// waves: 1, 2 or 4 (anything else: 4); super_restart: 1 on, else off;
+// simd_waves: 5 to 8, 0 = the compiler's own register budget, else the
+// default; keep_bottom: 0 off, else on
+JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int keep_bottom)
 {
     JitShape sh;
     if (!grad) {
+        sh.keep_bottom = keep_bottom != 0;
         sh.waves = waves == 1 ? 1 : waves == 2 ? 2 : 4;
         sh.super_restart = super_restart == 1;
+        sh.simd_waves = (simd_waves >= 5 && simd_waves <= 8) ? simd_waves : simd_waves == 0 ? 0 : kDefaultSimdWaves;
     }
     return sh;
 }
@@ -705,6 +722,7 @@ std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
          (!grad && sh.super_restart && P.N <= kSuperMaxNodes ? "true" : "false") + ";\n";
     // wavefronts per block (the launch uses the same)
     s += "  static constexpr int WAVES = " + std::to_string(sh.waves) + ";\n";
+    s += std::string("  static constexpr bool KEEPB = ") + (sh.keep_bottom ? "true" : "false") + ";\n";
     // relaxations of counter bits 11..16 (the chained iteration arcs)
     int ck[6] = {-1, -1, -1, -1, -1, -1};
     for (size_t k = 0; k < nr; ++k)
@@ -726,8 +744,11 @@ std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
              "  __shared__ bat::LdsTables L; __shared__ bat::LdsGrad LG;\n"
              "  bat::sweep_kernel<bat::StaticClosure<JitGraph, false>, true>(P, L, &LG);\n}\n";
     else
-        s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(bat::kWave * sh.waves) +
-             ") bat_fwd_jit(bat::KParams P) {\n"
+        s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(bat::kWave * sh.waves) + ")" +
+             (sh.simd_waves ? " __attribute__((amdgpu_waves_per_eu(" + std::to_string(sh.simd_waves) + ", " +
+                                  std::to_string(sh.simd_waves) + ")))"
+                            : std::string()) +
+             " bat_fwd_jit(bat::KParams P) {\n"
              "  __shared__ bat::LdsTables L;\n"
              "  bat::sweep_kernel<bat::StaticClosure<JitGraph>, false>(P, L, nullptr);\n}\n";
     return s;
@@ -738,7 +759,8 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
 {
     compile_ms = 0.0;
     std::string key = std::to_string(D.id) + (grad ? " grad " : " fwd ") + std::to_string(sh.waves) +
-                      (sh.super_restart ? "s " : " ") + P.structure;
+                      (sh.super_restart ? "s" : "") + (sh.keep_bottom ? "k" : "") + "/" +
+                      std::to_string(sh.simd_waves) + " " + P.structure;
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto it = g_jit.find(key);
     if (it != g_jit.end()) {
@@ -800,7 +822,8 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
 // ------------------------------------------------------------ autotune cache
 struct TuneChoice {
     int chunk_log2, check_every, jit, perm, chain = -1, order = -1;
-    int waves = -1, super_restart = -1;  // specialised forward launch shape (-1: default)
+    // specialised forward launch shape (-1: default)
+    int waves = -1, super_restart = -1, simd_waves = -1, keep_bottom = -1;
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneChoice> g_tune;
@@ -824,7 +847,7 @@ struct Request {
     bool grad;
     // forced knobs (autotuner); -1 = from options / the tuned choice
     int force_chunk_log2 = -1, force_check = -1, force_jit = -1, force_perm = -1, force_chain = -1,
-        force_order = -1, force_waves = -1, force_super = -1;
+        force_order = -1, force_waves = -1, force_super = -1, force_simd = -1, force_keep = -1;
     // timing sample (autotuner): sweep only this many work items, spread
     // over the whole counter by an odd multiplier (0 = everything)
     u64 sample_items = 0;
@@ -846,6 +869,8 @@ TuneChoice choose(const DeviceInfo &D, const std::string &gkey, bool grad, const
     if (O.item_order.load() >= 0) tc.order = (int)O.item_order.load();
     if (O.block_waves.load() >= 0) tc.waves = (int)O.block_waves.load();
     if (O.super_restart.load() >= 0) tc.super_restart = (int)O.super_restart.load();
+    if (O.simd_waves.load() >= 0) tc.simd_waves = (int)O.simd_waves.load();
+    if (O.keep_bottom.load() >= 0) tc.keep_bottom = (int)O.keep_bottom.load();
     if (rq) {
         if (rq->force_chunk_log2 >= 0) tc.chunk_log2 = rq->force_chunk_log2;
         if (rq->force_check >= 0) tc.check_every = rq->force_check;
@@ -855,6 +880,8 @@ TuneChoice choose(const DeviceInfo &D, const std::string &gkey, bool grad, const
         if (rq->force_order >= 0) tc.order = rq->force_order;
         if (rq->force_waves >= 0) tc.waves = rq->force_waves;
         if (rq->force_super >= 0) tc.super_restart = rq->force_super;
+        if (rq->force_simd >= 0) tc.simd_waves = rq->force_simd;
+        if (rq->force_keep >= 0) tc.keep_bottom = rq->force_keep;
     }
     return tc;
 }
@@ -1021,7 +1048,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     hipFunction_t jfn = nullptr;
     double jit_ms = 0.0;
     uint64_t kernel_id = 0;
-    const JitShape shape = jit_shape(rq.grad, tc.waves, tc.super_restart);
+    const JitShape shape = jit_shape(rq.grad, tc.waves, tc.super_restart, tc.simd_waves, tc.keep_bottom);
     if (use_jit) {
         int rc = jit_get(D, P, rq.grad, shape, jfn, jit_ms, kernel_id);
         if (rc) return rc;
@@ -1063,8 +1090,10 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     I.check_every = (int32_t)K.check_every;
     I.item_order = K.chunk_mul != 1 ? 1 : 0;
     I.block_waves = (int32_t)wpb;
-    I.super_restart = (use_jit && shape.super_restart && P.N <= kSuperMaxNodes) ? 1 : 0;
+    I.keep_bottom = (use_jit && !rq.grad && shape.keep_bottom && P.N <= bat::kKeepBottomMaxNodes) ? 1 : 0;
+    I.super_restart = (I.keep_bottom && shape.super_restart && P.N <= kSuperMaxNodes) ? 1 : 0;
     I.window_test = (int32_t)K.window_test;
+    I.simd_waves = use_jit ? shape.simd_waves : 0;
     t_state.have_launch = true;
     return BAT_OK;
 }
@@ -1326,7 +1355,9 @@ int bat_jit_source(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t
     make_plan(n, m, arcs, s, t, P, perm, (flags & BAT_DIRECTED) != 0);
     Options &O = opts();
     const std::string src =
-        jit_source(P, grad != 0, jit_shape(grad != 0, (int)O.block_waves.load(), (int)O.super_restart.load()));
+        jit_source(P, grad != 0,
+                   jit_shape(grad != 0, (int)O.block_waves.load(), (int)O.super_restart.load(), (int)O.simd_waves.load(),
+                             (int)O.keep_bottom.load()));
     const uint64_t need = (uint64_t)src.size() + 1;
     const uint64_t have = *len;
     *len = need;
@@ -1360,7 +1391,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         u64 target = (1ull << ubits) / ((u64)std::max(D.cus, 1) * 64ull);
         while (clog_auto < 12 && (2ull << clog_auto) <= target) ++clog_auto;
     }
-    struct Cand { int clog, check, jit, perm, chain, waves = -1, super_restart = -1; };
+    struct Cand { int clog, check, jit, perm, chain, waves = -1, super_restart = -1, simd_waves = -1; };
     constexpr double kTuneMargin = 0.01;
     auto measure = [&](const Cand &c, double &ns) -> bool {
         ns = 1e300;
@@ -1373,6 +1404,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
             tmpl.force_chain = c.chain;
             tmpl.force_waves = c.waves;
             tmpl.force_super = c.super_restart;
+            tmpl.force_simd = c.simd_waves;
             const int cl = c.clog > 0 ? c.clog : std::max(clog_auto, 3);
             const u64 per_item = 1ull << (cl + bat::kWordBits);
             tmpl.sample_items = std::max<u64>(1024, (1ull << 38) / per_item);
@@ -1393,10 +1425,10 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         const bool ok = measure(c, ns);
         if (verbose)
             fprintf(stderr,
-                    "bat_autotune: chunk_log2=%d check=%d jit=%d perm=%d chain=%d waves=%d super=%d -> %s %.6f "
-                    "ns/vector\n",
-                    c.clog, c.check, c.jit, c.perm, c.chain, c.waves, c.super_restart, ok ? "ok" : "failed",
-                    ok ? ns : 0.0);
+                    "bat_autotune: chunk_log2=%d check=%d jit=%d perm=%d chain=%d waves=%d super=%d simd=%d -> %s "
+                    "%.6f ns/vector\n",
+                    c.clog, c.check, c.jit, c.perm, c.chain, c.waves, c.super_restart, c.simd_waves,
+                    ok ? "ok" : "failed", ok ? ns : 0.0);
         // a later candidate must win by a margin: near ties keep the
         // earlier (default-first) choice, so repeated tuning agrees
         if (ok && ns < best * (1.0 - kTuneMargin)) {
@@ -1422,14 +1454,17 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         if (cl >= 5 && cl <= 14) consider({cl, w.check, w.jit, w.perm, w.chain});
     }
     consider({bc.clog, 2, bc.jit, bc.perm, bc.chain});
-    // launch shape of the specialised forward sweep: blocks of 2 wavefronts
-    // and the super-block store (which takes LDS, so whole 4-wavefront
-    // blocks wait for it)
+    // launch shape of the specialised forward sweep: the register budget
+    // (5 wavefronts per SIMD, or the compiler's own), then blocks of 2
+    // wavefronts and the super-block store (which takes LDS, so whole
+    // 4-wavefront blocks wait for it)
     if (bc.jit != 0) {
         const Cand w2 = bc;
-        consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, 4, 1});
-        consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, 2, 0});
-        consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, 2, 1});
+        consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, -1, -1, 5});
+        consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, -1, -1, 0});
+        const Cand w3 = bc;
+        consider({w3.clog, w3.check, w3.jit, w3.perm, w3.chain, 2, 0, w3.simd_waves});
+        consider({w3.clog, w3.check, w3.jit, w3.perm, w3.chain, 4, 1, w3.simd_waves});
     }
     if (total <= (1ull << 32)) consider({bc.clog, 1, 0, 0, 0});
     if (best >= 1e300) return fail(BAT_EDEVICE, "autotune: no candidate ran (%s)", t_err.c_str());
@@ -1439,6 +1474,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         TuneChoice tc{bc.clog, bc.check, bc.jit, bc.perm, bc.chain};
         tc.waves = bc.waves;
         tc.super_restart = bc.super_restart;
+        tc.simd_waves = bc.simd_waves;
         const std::string gk = graph_key(n, m, arcs, s, t);
         g_tune[std::to_string(D.id) + " fwd " + gk] = tc;
         g_tune[std::to_string(D.id) + " grad " + gk] = tc;

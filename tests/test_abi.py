@@ -107,7 +107,8 @@ def _hipcc():
 def test_jit_sources_compile(tmp_path, grad):
     """The graph-specialised kernel sources compile for gfx950 (the same text
     hiprtc gets, plus the runtime header hiprtc provides by itself); graphs
-    of up to 32 relevant nodes keep every reach word in registers."""
+    of up to 32 relevant nodes keep their reach words in registers inside
+    the convergence loops."""
     import subprocess
     import bat_workloads as W
     import paper_2209_09711_amd as B
@@ -132,20 +133,26 @@ def test_jit_sources_compile(tmp_path, grad):
         priv = [int(x) for x in re.findall(r"\.private_segment_fixed_size:\s+(\d+)", asm)]
         spill = [int(x) for x in re.findall(r"\.vgpr_spill_count:\s+(\d+)", asm)]
         assert priv and spill
-        if small and not grad:
-            assert max(priv) == 0 and max(spill) == 0, (net.name, priv, spill)
         if small:
-            # the gradient build asks for three wavefronts per SIMD: it may
-            # spill, but only in once-per-block or once-per-item code, never
-            # inside the per-iteration loops (loop depth >= 2)
-            depth, inner = 0, []
+            # Both builds ask the compiler for more wavefronts per SIMD than
+            # its own register budget gives (gradient 3, forward 6), so both
+            # may spill, but not inside the convergence loops: for the
+            # gradient nothing below the block loop (depth >= 2), for the
+            # forward at most a few reloads inside the sweeps of a chain
+            # step (depth >= 3: block loop, chain steps, sweeps), against
+            # some 700 instructions there.
+            limit = 2 if grad else 3
+            depth, inner, deepest = 0, [], 0
             for line in asm.splitlines():
                 if re.match(r"^(\.LBB\d+_\d+:|; %bb\.\d+:)", line):  # every block start
                     mm = re.search(r"Depth=(\d+)", line)
                     depth = int(mm.group(1)) if mm else 0
-                if "scratch_" in line and depth >= 2:
+                    deepest = max(deepest, depth)
+                if "scratch_" in line and depth >= limit:
                     inner.append(line.strip())
-            assert not inner, (net.name, directed, inner[:4])
+            assert len(inner) <= (0 if grad else 4), (net.name, directed, inner[:4])
+            if not grad:
+                assert deepest == 3, (net.name, deepest)
     with pytest.raises(B.BatError):
         B.bat_jit_source(3, [(0, 1), (1, 2)], 0, 2, perm=9)
 

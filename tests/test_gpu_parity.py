@@ -459,29 +459,35 @@ def test_window_test(perm, k):
             assert r.count == o.count and rel_ok(r.R, o.sum), (lo, hi)
 
 
-@pytest.mark.parametrize("waves,super_restart", [(1, 0), (1, 1), (2, 0), (2, 1), (4, 0), (4, 1)])
-def test_forward_launch_shapes(waves, super_restart):
-    """Blocks of 1, 2 or 4 wavefronts, with or without the super-block store,
-    sweep the same vectors: the launch reports the shape it ran, whole
-    sweeps agree bit for bit with the default shape and with the frontier DP,
-    and ragged ranges agree with the oracle."""
+@pytest.mark.parametrize("waves,super_restart,simd,keep", [
+    (1, 0, 6, 1), (1, 1, 6, 1), (2, 0, 6, 1), (2, 1, 6, 1), (4, 0, 6, 1), (4, 1, 6, 1),
+    (4, 0, 0, 1), (4, 0, 5, 1), (4, 0, 8, 1), (4, 0, 6, 0), (4, 1, 0, 0)])
+def test_forward_launch_shapes(waves, super_restart, simd, keep):
+    """Blocks of 1, 2 or 4 wavefronts, with or without the super-block store
+    and the kept block bottoms, compiled for 4 (the compiler's budget) to 8
+    wavefronts per SIMD, sweep the same vectors: the launch reports the
+    shape it ran, whole sweeps agree bit for bit with the default shape and
+    with the frontier DP, and ragged ranges agree with the oracle."""
     B = _B()
     nets = [W.grid(4, 5, p=np.random.default_rng(6).uniform(0.6, 0.99, 31)), W.config4()]
     for net in nets:
-        say("shape", waves, super_restart, net.name)
+        say("shape", waves, super_restart, simd, keep, net.name)
         with options(BAT_JIT=1, BAT_AUTOTUNE=0, BAT_PERM=3, BAT_CHAIN_LOG2=3):
             ref = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
-            with options(BAT_BLOCK_WAVES=waves, BAT_SUPER_RESTART=super_restart):
+            with options(BAT_BLOCK_WAVES=waves, BAT_SUPER_RESTART=super_restart, BAT_SIMD_WAVES=simd,
+                         BAT_KEEP_BOTTOM=keep):
                 got = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
                 li = B.bat_last_launch()
-        assert li.specialised == 1 and li.block_waves == waves and li.super_restart == super_restart
+        assert li.specialised == 1 and li.block_waves == waves and li.simd_waves == simd
+        assert li.keep_bottom == keep and li.super_restart == (super_restart and keep)
         assert got == ref
         if net.m <= 31:
             Rd, cd = frontier_dp.reliability(net.n, net.arcs, net.p, net.s, net.t)
             assert got[1] == cd and rel_ok(got[0], Rd)
     net = nets[0]
-    rng = np.random.default_rng(40 + waves + super_restart)
-    with options(BAT_JIT=1, BAT_BLOCK_WAVES=waves, BAT_SUPER_RESTART=super_restart, BAT_CHUNK_LOG2=7):
+    rng = np.random.default_rng(40 + waves + super_restart + simd + keep)
+    with options(BAT_JIT=1, BAT_BLOCK_WAVES=waves, BAT_SUPER_RESTART=super_restart, BAT_SIMD_WAVES=simd,
+                 BAT_KEEP_BOTTOM=keep, BAT_CHUNK_LOG2=7):
         for _ in range(2):
             lo = int(rng.integers(0, (1 << net.m) - (1 << 20)))
             hi = lo + int(rng.integers(1 << 17, 1 << 20))
