@@ -41,7 +41,13 @@ PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 1.26e15 bit-ops/s
 #     WRITE_SIZE x 1.0 (KiB), the factors of a plain 1 GiB device copy;
 #   valu_busy: SQ_INSTS_VALU / (256 CUs x GRBM_GUI_ACTIVE cycles);
 #   valu_insts_per_vector: SQ_INSTS_VALU x 64 lanes / 2^40 (lane-ops).
-MEASURED = {}
+MEASURED = {
+    "7580c190c55bd32e/perm3/chunk12/chain3/check1/order1/waves4/super0/window1/simd6/keep1": {
+        "traffic_bytes": (291131.875 * 2.0 + 104580906.71875 * 1.0) * 1024,
+        "valu_busy": 0.82,
+        "valu_insts_per_vector": 3.99,
+    },
+}
 
 
 def launch_key(li) -> str:
@@ -225,6 +231,7 @@ def main():
                    "vectors_per_step": nvec},
         "R": R,
         "R_hex": R.hex(),
+        "launch": launch_key(li_step),
         "feasible_count": count,
         "time_to_exact_R_s": {"cold_incl_jit": cold_s, "warm": warm_s, "jit_compile_ms": jit_ms,
                               "cold_from_disk_cache": cold_cached_s, "jit_cache_load_ms": load_ms,
