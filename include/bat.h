@@ -221,8 +221,8 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
  *                      cover distant parts of the counter), 0 = counter
  *                      order; R and counts never depend on it beyond
  *                      floating-point rounding
- *   "BAT_WINDOW_TEST"  1 (default) = the graph-specialised forward sweep
- *                      tests each window of 2048 iterations once, with all
+ *   "BAT_WINDOW_TEST"  1 (default) = the graph-specialised sweeps (R, and
+ *                      R with the gradient) test each window of 2048 iterations once, with all
  *                      11 word arcs up, and skips the chained blocks whose
  *                      last iteration cannot connect s and t (none of their
  *                      vectors can); 0 = sweep every block.  Results are

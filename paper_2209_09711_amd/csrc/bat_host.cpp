@@ -975,7 +975,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     K.check_every = tc.check_every >= 2 ? 2u : 1u;
     K.chain = chain ? ck : 0u;
     K.ncol = rq.grad ? 1u + 2u * m : 1u;
-    K.window_test = (chain && !rq.grad && O.window_test.load() != 0) ? 1u : 0u;
+    K.window_test = (chain && O.window_test.load() != 0) ? 1u : 0u;
     K.n_nodes = (u32)P.N;
     K.s = (u32)P.S;
     K.t = (u32)P.T;
@@ -1098,7 +1098,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     I.block_waves = (int32_t)wpb;
     I.keep_bottom = (use_jit && !rq.grad && shape.keep_bottom && P.N <= bat::kKeepBottomMaxNodes) ? 1 : 0;
     I.super_restart = (I.keep_bottom && shape.super_restart && P.N <= kSuperMaxNodes) ? 1 : 0;
-    I.window_test = (int32_t)K.window_test;
+    I.window_test = use_jit ? (int32_t)K.window_test : 0;
     I.simd_waves = (use_jit && !(rq.grad && P.N > kGradThreeWaveNodes)) ? shape.simd_waves : 0;
     t_state.have_launch = true;
     return BAT_OK;

@@ -435,18 +435,24 @@ def test_chain_lengths(k):
 def test_window_test(perm, k):
     """Skipping the chained blocks whose top iteration cannot connect s and t
     even with all 11 word arcs up changes nothing: whole sweeps of a grid
-    (where about half the blocks are skipped) match the unskipped sweep
-    bit for bit and the frontier DP; ranges that start and end inside
-    windows and blocks agree with the oracle."""
+    (where about half the blocks are skipped), with and without the
+    gradient, match the unskipped sweeps and the frontier DP; ranges that
+    start and end inside windows and blocks agree with the oracle."""
     B = _B()
     net = W.grid(4, 5, p=np.random.default_rng(5).uniform(0.6, 0.99, 31))
     say("window test", perm, k, net.name)
-    res = {}
+    res, grads = {}, {}
     for wt in (0, 1):
         with options(BAT_WINDOW_TEST=wt, BAT_PERM=perm, BAT_CHAIN_LOG2=k, BAT_JIT=1, BAT_AUTOTUNE=0):
             res[wt] = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
-            assert B.bat_last_launch().specialised == 1
+            li = B.bat_last_launch()
+            assert li.specialised == 1 and li.window_test == wt
+            grads[wt] = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+            assert B.bat_last_launch().window_test == wt
     assert res[0] == res[1]
+    g0, g1 = grads[0], grads[1]
+    assert g0.count == g1.count == res[1][1] and rel_ok(g1.R, g0.R, 1e-15)
+    assert np.allclose(g1.T1, g0.T1, rtol=1e-14, atol=0) and np.allclose(g1.T0, g0.T0, rtol=1e-14, atol=0)
     Rd, cd = frontier_dp.reliability(net.n, net.arcs, net.p, net.s, net.t)
     assert res[1][1] == cd and rel_ok(res[1][0], Rd)
     rng = np.random.default_rng(100 + k + perm)
