@@ -286,8 +286,8 @@ typedef struct {
     int32_t chunk_log2;    /* work-item size used */
     int32_t n_chunks;      /* wavefront work items */
     int32_t relaxations;   /* arc relaxations per sweep after pruning */
-    uint64_t kernel_id;    /* 64-bit hash naming the exact kernel code that ran (the specialised source
-                              text and compile options, or the ahead-of-time kernel sources and instance) */
+    uint64_t kernel_id;    /* 64-bit hash naming the exact kernel code that ran (the specialised
+                              kernel's code object, or the ahead-of-time kernel sources and instance) */
     int32_t perm;          /* arc-to-counter-bit order (as "BAT_PERM"; 4 = forward BAT order; -1 batched) */
     int32_t chain_log2;    /* warm-start chain length used, 0 = none */
     int32_t check_every;   /* convergence-test cadence */

@@ -559,7 +559,7 @@ int events_ready()
 struct JitEntry {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
-    uint64_t id = 0;  // hash of the source text and compile options
+    uint64_t id = 0;  // hash of the compiled code object
 };
 std::mutex g_jit_mu;
 std::map<std::string, JitEntry> g_jit;
@@ -781,12 +781,14 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
     std::string keytext = src;
     for (const char *opt : o) keytext += std::string("\n//") + opt;
     const CacheKey ck = cache_key(keytext);
-    id = ck.h1;
     const std::string cdir = cache_dir();
     std::vector<char> code;
+    // the kernel's identity: its machine code, so that edits which leave
+    // the code alone (comments) keep it
+    auto code_id = [&]() { return cache_key(std::string(code.begin(), code.end())).h1; };
     if (!cdir.empty() && cache_read(cache_path(cdir, ck), ck, code)) {
         JitEntry e;
-        e.id = id;
+        e.id = id = code_id();
         if (hipModuleLoadData(&e.mod, code.data()) == hipSuccess &&
             hipModuleGetFunction(&e.fn, e.mod, grad ? "bat_grad_jit" : "bat_fwd_jit") == hipSuccess) {
             g_jit.emplace(key, e);
@@ -816,7 +818,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
     hiprtcDestroyProgram(&prog);
     if (!cdir.empty()) cache_write(cache_path(cdir, ck), ck, code);
     JitEntry e;
-    e.id = id;
+    e.id = id = code_id();
     HIPCHK(hipModuleLoadData(&e.mod, code.data()));
     HIPCHK(hipModuleGetFunction(&e.fn, e.mod, grad ? "bat_grad_jit" : "bat_fwd_jit"));
     g_jit.emplace(key, e);
