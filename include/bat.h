@@ -242,6 +242,11 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
  *                      chained block's bottom closure in registers and
  *                      resume later chain starts from it, 0 = solve chain
  *                      starts afresh, -1 = tuned (else 1)
+ *   "BAT_SERIES"       1 (default) = the graph-specialised kernels join two
+ *                      arcs in series through a node of degree 2 (other
+ *                      than s and t) into one relaxation with the AND of
+ *                      their masks, which removes the node; 0 = relax
+ *                      every arc.  Results are identical either way
  *   "BAT_JIT_FLUSH"    setting it to a nonzero value unloads every
  *                      graph-specialised kernel this process compiled or
  *                      loaded (after the current device finishes its work;

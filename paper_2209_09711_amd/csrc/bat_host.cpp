@@ -68,7 +68,8 @@ int fail(int code, const char *fmt, ...)
 // ------------------------------------------------------------ options
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
-        window_test{1}, block_waves{-1}, super_restart{-1}, simd_waves{-1}, keep_bottom{-1}, jit_flush_req{0};
+        window_test{1}, block_waves{-1}, super_restart{-1}, simd_waves{-1}, keep_bottom{-1}, series{1},
+        jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -88,6 +89,7 @@ struct Options {
         rd("BAT_SUPER_RESTART", super_restart);
         rd("BAT_SIMD_WAVES", simd_waves);
         rd("BAT_KEEP_BOTTOM", keep_bottom);
+        rd("BAT_SERIES", series);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -105,6 +107,7 @@ struct Options {
         if (!strcmp(k, "BAT_SUPER_RESTART")) return &super_restart;
         if (!strcmp(k, "BAT_SIMD_WAVES")) return &simd_waves;
         if (!strcmp(k, "BAT_KEEP_BOTTOM")) return &keep_bottom;
+        if (!strcmp(k, "BAT_SERIES")) return &series;
         if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
@@ -188,6 +191,11 @@ struct Plan {
     int N = 0, S = 0, T = 0;              // relevant nodes, renumbered
     std::vector<int> ru, rv, rb, rd;      // relaxations (forward order): nodes, counter bit, discovers rv
     std::vector<u32> code, wconst;        // the same for the generic kernel
+    // The graph-specialised kernel's relaxations: as above, after series
+    // contraction (undirected graphs), so a relaxation may stand for two
+    // arcs in series; rb2 is the second arc's counter bit, -1 for one arc.
+    int jN = 0, jS = 0, jT = 0;
+    std::vector<int> jru, jrv, jrb, jrb2, jrd;
     std::vector<u32> prog;                // code/wconst pairs, groups of 4, forward then backward
     std::string structure;                // JIT key (graph structure only)
 };
@@ -252,6 +260,79 @@ void assign_bits(int m, const std::vector<int> &rel_bfs, const std::vector<char>
     }
     for (int i = m - 1; i >= 0; --i) take(i);
     for (int c = 0; c < m; ++c) cb_of_arc[by_cb[c]] = c;
+}
+
+// The specialised kernel's relaxation list.  In an undirected graph a
+// node other than s and t with exactly two relevant arcs, to two different
+// neighbours u and w, only ever passes reach between them: it is reached
+// from u through its first arc or from w through its second, and it passes
+// on nothing else.  Removing it and joining u and w by one relaxation whose
+// working mask is the AND of the two arcs' masks leaves every other node's
+// reach, t's in particular, exactly as it was.  Only pairs of real arcs are
+// joined (a relaxation stands for at most two arcs).  Digraphs keep the
+// plain list.
+void contract_series(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, const std::vector<char> &rel,
+                     Plan &P)
+{
+    struct VArc {
+        int u, v, b1, b2;
+    };
+    std::vector<VArc> va;
+    std::vector<std::vector<int>> inc(n);  // relevant arcs at each node
+    for (int i = 0; i < m; ++i)
+        if (rel[i] && arcs[i].u != arcs[i].v) {
+            inc[arcs[i].u].push_back(i);
+            inc[arcs[i].v].push_back(i);
+        }
+    std::vector<char> used(m, 0), gone(n, 0);
+    if (!P.directed && opts().series.load() != 0) {
+        for (int v = 0; v < n; ++v) {
+            if (v == s || v == t || inc[v].size() != 2) continue;
+            const int a = inc[v][0], b = inc[v][1];
+            if (used[a] || used[b]) continue;
+            const int u = arcs[a].u == v ? arcs[a].v : arcs[a].u;
+            const int w = arcs[b].u == v ? arcs[b].v : arcs[b].u;
+            if (u == w || gone[u] || gone[w]) continue;
+            used[a] = used[b] = 1;
+            gone[v] = 1;
+            va.push_back({u, w, P.cb_of_arc[a], P.cb_of_arc[b]});
+        }
+    }
+    for (int i = 0; i < m; ++i)
+        if (rel[i] && !used[i] && arcs[i].u != arcs[i].v) va.push_back({arcs[i].u, arcs[i].v, P.cb_of_arc[i], -1});
+    // BFS from s in arc-list order, as for the plain list
+    std::vector<int> id(n, -1), order{s};
+    std::vector<char> listed(va.size(), 0);
+    id[s] = 0;
+    P.jru.clear(); P.jrv.clear(); P.jrb.clear(); P.jrb2.clear(); P.jrd.clear();
+    for (size_t h = 0; h < order.size(); ++h) {
+        const int x = order[h];
+        for (size_t k = 0; k < va.size(); ++k) {
+            if (listed[k]) continue;
+            const VArc &e = va[k];
+            if (P.directed ? e.u != x : (e.u != x && e.v != x)) continue;
+            const int y = e.u == x ? e.v : e.u;
+            int disc = 0;
+            if (id[y] < 0) {
+                id[y] = (int)order.size();
+                order.push_back(y);
+                disc = 1;
+            }
+            listed[k] = 1;
+            P.jru.push_back(id[x]);
+            P.jrv.push_back(id[y]);
+            P.jrb.push_back(e.b1);
+            P.jrb2.push_back(e.b2);
+            P.jrd.push_back(disc);
+        }
+    }
+    if (id[t] < 0) {
+        id[t] = (int)order.size();
+        order.push_back(t);
+    }
+    P.jN = (int)order.size();
+    P.jS = 0;
+    P.jT = id[t];
 }
 
 void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, Plan &P, int perm_kind = 0,
@@ -388,11 +469,12 @@ void make_plan(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, 
             P.prog[ng * 8 + 2 * kb + 1] = P.wconst[k];
         }
     }
-    std::string sdesc = std::string(directed ? "D " : "") + "N" + std::to_string(P.N) + " S" + std::to_string(P.S) + " T" + std::to_string(P.T) +
-                        " m" + std::to_string(m) + " :";
-    for (size_t k = 0; k < P.ru.size(); ++k)
-        sdesc += " " + std::to_string(P.ru[k]) + "," + std::to_string(P.rv[k]) + "," + std::to_string(P.rb[k]) +
-                 (P.rd[k] ? "d" : "");
+    contract_series(n, m, arcs, s, t, rel, P);
+    std::string sdesc = std::string(directed ? "D " : "") + "N" + std::to_string(P.jN) + " S" + std::to_string(P.jS) +
+                        " T" + std::to_string(P.jT) + " m" + std::to_string(m) + " :";
+    for (size_t k = 0; k < P.jru.size(); ++k)
+        sdesc += " " + std::to_string(P.jru[k]) + "," + std::to_string(P.jrv[k]) + "," + std::to_string(P.jrb[k]) +
+                 (P.jrb2[k] >= 0 ? "&" + std::to_string(P.jrb2[k]) : std::string()) + (P.jrd[k] ? "d" : "");
     P.structure = sdesc;
 }
 
@@ -704,10 +786,10 @@ std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
     s.reserve(strlen(kDeviceSource) + 4096);
     s += kDeviceSource;
     s += "\nstruct JitGraph {\n";
-    s += "  static constexpr int N = " + std::to_string(P.N) + ";\n";
-    s += "  static constexpr int S = " + std::to_string(P.S) + ";\n";
-    s += "  static constexpr int T = " + std::to_string(P.T) + ";\n";
-    size_t nr = P.ru.size();
+    s += "  static constexpr int N = " + std::to_string(P.jN) + ";\n";
+    s += "  static constexpr int S = " + std::to_string(P.jS) + ";\n";
+    s += "  static constexpr int T = " + std::to_string(P.jT) + ";\n";
+    size_t nr = P.jru.size();
     s += "  static constexpr int NR = " + std::to_string(nr) + ";\n";
     auto arr = [&](const char *name, const std::vector<int> &v) {
         s += std::string("  static constexpr unsigned char ") + name + "[" + std::to_string(nr ? nr : 1) + "] = {";
@@ -715,23 +797,31 @@ std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
         for (size_t k = 0; k < nr; ++k) s += (k ? "," : "") + std::to_string(v[k]);
         s += "};\n";
     };
-    arr("RU", P.ru);
-    arr("RV", P.rv);
-    arr("RB", P.rb);
-    arr("RD", P.rd);
+    arr("RU", P.jru);
+    arr("RV", P.jrv);
+    arr("RB", P.jrb);
+    arr("RD", P.jrd);
+    // second counter bit of a relaxation that joins two arcs in series
+    // (255: one arc)
+    {
+        std::vector<int> b2(nr);
+        for (size_t k = 0; k < nr; ++k) b2[k] = P.jrb2[k] < 0 ? 255 : P.jrb2[k];
+        arr("RB2", b2);
+    }
     s += std::string("  static constexpr bool DIR = ") + (P.directed ? "true" : "false") + ";\n";
     // forward sweeps of graphs small enough for the LDS store (4 blocks of
     // 4 wavefronts per CU keep (N + 2) words per lane each) also resume
     // block bottoms from the kept bottom of their 2^6-aligned super-block
     s += std::string("  static constexpr bool SUPER = ") +
-         (!grad && sh.super_restart && P.N <= kSuperMaxNodes ? "true" : "false") + ";\n";
+         (!grad && sh.super_restart && P.jN <= kSuperMaxNodes ? "true" : "false") + ";\n";
     // wavefronts per block (the launch uses the same)
     s += "  static constexpr int WAVES = " + std::to_string(sh.waves) + ";\n";
     s += std::string("  static constexpr bool KEEPB = ") + (sh.keep_bottom ? "true" : "false") + ";\n";
     // relaxations of counter bits 11..16 (the chained iteration arcs)
     int ck[6] = {-1, -1, -1, -1, -1, -1};
     for (size_t k = 0; k < nr; ++k)
-        if (P.rb[k] >= bat::kWordBits && P.rb[k] < bat::kWordBits + 6) ck[P.rb[k] - bat::kWordBits] = (int)k;
+        for (int b : {P.jrb[k], P.jrb2[k]})
+            if (b >= bat::kWordBits && b < bat::kWordBits + 6) ck[b - bat::kWordBits] = (int)k;
     s += "  static constexpr int CK[6] = {";
     for (int b = 0; b < 6; ++b) s += (b ? "," : "") + std::to_string(ck[b]);
     s += "};\n";
@@ -739,7 +829,7 @@ std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
     // the gradient sweep of a small graph fits three wavefronts per SIMD
     // with spills confined to once-per-segment code; larger graphs keep the
     // compiler's register budget
-    if (grad && P.N <= kGradThreeWaveNodes && sh.simd_waves)
+    if (grad && P.jN <= kGradThreeWaveNodes && sh.simd_waves)
         s += "extern \"C\" __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(" +
              std::to_string(sh.simd_waves) + ", " + std::to_string(sh.simd_waves) + ")))\n"
              "bat_grad_jit(bat::KParams P) {\n"
@@ -1091,17 +1181,17 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     I.specialised = use_jit ? 1 : 0;
     I.chunk_log2 = clog;
     I.n_chunks = (int32_t)std::min<u64>(K.n_chunks, 0x7fffffff);
-    I.relaxations = (int32_t)P.code.size();
+    I.relaxations = (int32_t)(use_jit ? P.jru.size() : P.code.size());
     I.kernel_id = kernel_id;
     I.perm = P.perm;
     I.chain_log2 = (int32_t)K.chain;
     I.check_every = (int32_t)K.check_every;
     I.item_order = K.chunk_mul != 1 ? 1 : 0;
     I.block_waves = (int32_t)wpb;
-    I.keep_bottom = (use_jit && !rq.grad && shape.keep_bottom && P.N <= bat::kKeepBottomMaxNodes) ? 1 : 0;
-    I.super_restart = (I.keep_bottom && shape.super_restart && P.N <= kSuperMaxNodes) ? 1 : 0;
+    I.keep_bottom = (use_jit && !rq.grad && shape.keep_bottom && P.jN <= bat::kKeepBottomMaxNodes) ? 1 : 0;
+    I.super_restart = (I.keep_bottom && shape.super_restart && P.jN <= kSuperMaxNodes) ? 1 : 0;
     I.window_test = use_jit ? (int32_t)K.window_test : 0;
-    I.simd_waves = (use_jit && !(rq.grad && P.N > kGradThreeWaveNodes)) ? shape.simd_waves : 0;
+    I.simd_waves = (use_jit && !(rq.grad && P.jN > kGradThreeWaveNodes)) ? shape.simd_waves : 0;
     t_state.have_launch = true;
     return BAT_OK;
 }

@@ -502,6 +502,36 @@ def test_forward_launch_shapes(waves, super_restart, simd, keep):
             assert r.count == o.count and rel_ok(r.R, o.sum), (lo, hi)
 
 
+def test_series_joining():
+    """Joining two arcs in series through a degree-2 node into one relaxation
+    (the AND of their masks) changes nothing: R, counts and gradients match
+    the plain relaxation list and the oracle, on graphs with many such
+    nodes (paths of parallel series, a ladder, random sparse graphs)."""
+    B = _B()
+    rng = np.random.default_rng(515)
+    nets = [W.parallel_paths(4, np.full(8, 0.9)), W.series(12, np.linspace(0.5, 0.99, 12)), W.grid(2, 12),
+            W.grid(4, 5, p=rng.uniform(0.6, 0.99, 31))]
+    for seed in range(4):
+        nets.append(W.random_connected(16, 20, seed=700 + seed, p_lo=0.3, p_hi=0.99))
+    for net in nets:
+        say("series", net.name, net.n, net.m)
+        out = {}
+        for sj in (0, 1):
+            with options(BAT_JIT=1, BAT_SERIES=sj, BAT_AUTOTUNE=0):
+                R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+                li = B.bat_last_launch()
+                g = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+            out[sj] = (R, cnt, g, li.relaxations)
+        assert out[0][1] == out[1][1] == out[1][2].count
+        assert rel_ok(out[1][0], out[0][0], 1e-14) and rel_ok(out[1][2].R, out[0][2].R, 1e-14)
+        assert np.allclose(out[1][2].T1, out[0][2].T1, rtol=1e-13, atol=0)
+        assert np.allclose(out[1][2].T0, out[0][2].T0, rtol=1e-13, atol=0)
+        assert out[1][3] <= out[0][3]
+        if net.m <= 24:
+            o = oracle.net_reliability(net)
+            assert out[1][1] == o.count and rel_ok(out[1][0], o.sum)
+
+
 @pytest.mark.parametrize("order", [0, 1])
 def test_item_orders(order):
     """Counter-order and spread work-item orders sweep the same vectors: equal
