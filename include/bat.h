@@ -240,8 +240,9 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
  *                      compiler's own budget, -1 = tuned (else 6)
  *   "BAT_KEEP_BOTTOM"  graph-specialised forward sweep: 1 = keep each
  *                      chained block's bottom closure in registers and
- *                      resume later chain starts from it, 0 = solve chain
- *                      starts afresh, -1 = tuned (else 1)
+ *                      resume later chain starts from it, 2 = keep it in
+ *                      LDS instead, 0 = solve chain starts afresh,
+ *                      -1 = tuned (else 1)
  *   "BAT_SERIES"       1 (default) = the graph-specialised kernels join two
  *                      arcs in series through a node of degree 2 (other
  *                      than s and t) into one relaxation with the AND of
@@ -301,7 +302,7 @@ typedef struct {
     int32_t super_restart; /* 1 if block bottoms resume from a kept super-block bottom */
     int32_t window_test;   /* 1 if chained blocks that cannot connect s and t were skipped */
     int32_t simd_waves;    /* wavefronts per SIMD the kernel was compiled to fit, 0 = compiler's choice */
-    int32_t keep_bottom;   /* 1 if chain starts resumed from the block bottom kept in registers */
+    int32_t keep_bottom;   /* chain starts resumed from the kept block bottom: 1 in registers, 2 in LDS */
     int32_t reserved;
 } bat_launch_info;
 

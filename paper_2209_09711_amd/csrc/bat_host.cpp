@@ -750,7 +750,8 @@ struct JitShape {
     int waves = bat::kWavesPerBlock;
     bool super_restart = false;
     int simd_waves = 0;  // > 0: ask the compiler to fit this many wavefronts per SIMD
-    bool keep_bottom = true;  // chain starts resume from the block bottom kept in registers
+    bool keep_bottom = true;  // chain starts resume from the kept block bottom
+    bool bottom_lds = false;  // ... kept in LDS instead of registers
 };
 
 // Default shape of the forward sweep: 4 wavefronts per block, kept block
@@ -773,6 +774,7 @@ JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int 
         sh.simd_waves = 3;
     } else {
         sh.keep_bottom = keep_bottom != 0;
+        sh.bottom_lds = keep_bottom == 2;
         sh.waves = waves == 1 ? 1 : waves == 2 ? 2 : 4;
         sh.super_restart = super_restart == 1;
         sh.simd_waves = (simd_waves >= 5 && simd_waves <= 8) ? simd_waves : simd_waves == 0 ? 0 : kDefaultSimdWaves;
@@ -817,6 +819,7 @@ std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
     // wavefronts per block (the launch uses the same)
     s += "  static constexpr int WAVES = " + std::to_string(sh.waves) + ";\n";
     s += std::string("  static constexpr bool KEEPB = ") + (sh.keep_bottom ? "true" : "false") + ";\n";
+    s += std::string("  static constexpr bool BOTTOM_LDS = ") + (sh.bottom_lds ? "true" : "false") + ";\n";
     // relaxations of counter bits 11..16 (the chained iteration arcs)
     int ck[6] = {-1, -1, -1, -1, -1, -1};
     for (size_t k = 0; k < nr; ++k)
@@ -855,7 +858,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
 {
     compile_ms = 0.0;
     std::string key = std::to_string(D.id) + (grad ? " grad " : " fwd ") + std::to_string(sh.waves) +
-                      (sh.super_restart ? "s" : "") + (sh.keep_bottom ? "k" : "") + "/" +
+                      (sh.super_restart ? "s" : "") + (sh.keep_bottom ? (sh.bottom_lds ? "K" : "k") : "") + "/" +
                       std::to_string(sh.simd_waves) + " " + P.structure;
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto it = g_jit.find(key);
@@ -1188,7 +1191,8 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     I.check_every = (int32_t)K.check_every;
     I.item_order = K.chunk_mul != 1 ? 1 : 0;
     I.block_waves = (int32_t)wpb;
-    I.keep_bottom = (use_jit && !rq.grad && shape.keep_bottom && P.jN <= bat::kKeepBottomMaxNodes) ? 1 : 0;
+    I.keep_bottom =
+        (use_jit && !rq.grad && shape.keep_bottom && P.jN <= bat::kKeepBottomMaxNodes) ? (shape.bottom_lds ? 2 : 1) : 0;
     I.super_restart = (I.keep_bottom && shape.super_restart && P.jN <= kSuperMaxNodes) ? 1 : 0;
     I.window_test = use_jit ? (int32_t)K.window_test : 0;
     I.simd_waves = (use_jit && !(rq.grad && P.jN > kGradThreeWaveNodes)) ? shape.simd_waves : 0;
@@ -1489,7 +1493,9 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         u64 target = (1ull << ubits) / ((u64)std::max(D.cus, 1) * 64ull);
         while (clog_auto < 12 && (2ull << clog_auto) <= target) ++clog_auto;
     }
-    struct Cand { int clog, check, jit, perm, chain, waves = -1, super_restart = -1, simd_waves = -1; };
+    struct Cand {
+        int clog, check, jit, perm, chain, waves = -1, super_restart = -1, simd_waves = -1, keep_bottom = -1;
+    };
     constexpr double kTuneMargin = 0.01;
     auto measure = [&](const Cand &c, double &ns) -> bool {
         ns = 1e300;
@@ -1503,6 +1509,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
             tmpl.force_waves = c.waves;
             tmpl.force_super = c.super_restart;
             tmpl.force_simd = c.simd_waves;
+            tmpl.force_keep = c.keep_bottom;
             const int cl = c.clog > 0 ? c.clog : std::max(clog_auto, 3);
             const u64 per_item = 1ull << (cl + bat::kWordBits);
             tmpl.sample_items = std::max<u64>(1024, (1ull << 38) / per_item);
@@ -1523,9 +1530,9 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         const bool ok = measure(c, ns);
         if (verbose)
             fprintf(stderr,
-                    "bat_autotune: chunk_log2=%d check=%d jit=%d perm=%d chain=%d waves=%d super=%d simd=%d -> %s "
-                    "%.6f ns/vector\n",
-                    c.clog, c.check, c.jit, c.perm, c.chain, c.waves, c.super_restart, c.simd_waves,
+                    "bat_autotune: chunk_log2=%d check=%d jit=%d perm=%d chain=%d waves=%d super=%d simd=%d "
+                    "keep=%d -> %s %.6f ns/vector\n",
+                    c.clog, c.check, c.jit, c.perm, c.chain, c.waves, c.super_restart, c.simd_waves, c.keep_bottom,
                     ok ? "ok" : "failed", ok ? ns : 0.0);
         // a later candidate must win by a margin: near ties keep the
         // earlier (default-first) choice, so repeated tuning agrees
@@ -1561,8 +1568,11 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, -1, -1, 5});
         consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, -1, -1, 0});
         const Cand w3 = bc;
-        consider({w3.clog, w3.check, w3.jit, w3.perm, w3.chain, 2, 0, w3.simd_waves});
-        consider({w3.clog, w3.check, w3.jit, w3.perm, w3.chain, 4, 1, w3.simd_waves});
+        // the kept block bottom in LDS: no spills for it, but fewer blocks fit
+        consider({w3.clog, w3.check, w3.jit, w3.perm, w3.chain, -1, -1, w3.simd_waves, 2});
+        const Cand w4 = bc;
+        consider({w4.clog, w4.check, w4.jit, w4.perm, w4.chain, 2, 0, w4.simd_waves, w4.keep_bottom});
+        consider({w4.clog, w4.check, w4.jit, w4.perm, w4.chain, 4, 1, w4.simd_waves, w4.keep_bottom});
     }
     if (total <= (1ull << 32)) consider({bc.clog, 1, 0, 0, 0});
     if (best >= 1e300) return fail(BAT_EDEVICE, "autotune: no candidate ran (%s)", t_err.c_str());
@@ -1573,6 +1583,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         tc.waves = bc.waves;
         tc.super_restart = bc.super_restart;
         tc.simd_waves = bc.simd_waves;
+        tc.keep_bottom = bc.keep_bottom;
         const std::string gk = graph_key(n, m, arcs, s, t);
         g_tune[std::to_string(D.id) + " fwd " + gk] = tc;
         g_tune[std::to_string(D.id) + " grad " + gk] = tc;
