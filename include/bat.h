@@ -243,6 +243,10 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
  *                      resume later chain starts from it, 2 = keep it in
  *                      LDS instead, 0 = solve chain starts afresh,
  *                      -1 = tuned (else 1)
+ *   "BAT_GRAD_KEEP_BOTTOM" graph-specialised gradient sweep: 2 (default) =
+ *                      keep each chained block's bottom closure in LDS and
+ *                      resume later chain starts from it, 0 = solve chain
+ *                      starts afresh
  *   "BAT_SERIES"       1 (default) = the graph-specialised kernels join two
  *                      arcs in series through a node of degree 2 (other
  *                      than s and t) into one relaxation with the AND of

@@ -69,7 +69,7 @@ int fail(int code, const char *fmt, ...)
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
         window_test{1}, block_waves{-1}, super_restart{-1}, simd_waves{-1}, keep_bottom{-1}, series{1},
-        jit_flush_req{0};
+        grad_keep_bottom{2}, jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -90,6 +90,7 @@ struct Options {
         rd("BAT_SIMD_WAVES", simd_waves);
         rd("BAT_KEEP_BOTTOM", keep_bottom);
         rd("BAT_SERIES", series);
+        rd("BAT_GRAD_KEEP_BOTTOM", grad_keep_bottom);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -108,6 +109,7 @@ struct Options {
         if (!strcmp(k, "BAT_SIMD_WAVES")) return &simd_waves;
         if (!strcmp(k, "BAT_KEEP_BOTTOM")) return &keep_bottom;
         if (!strcmp(k, "BAT_SERIES")) return &series;
+        if (!strcmp(k, "BAT_GRAD_KEEP_BOTTOM")) return &grad_keep_bottom;
         if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
@@ -772,6 +774,9 @@ JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int 
         // fits 3 wavefronts per SIMD without spilling; on the 36-arc random
         // graph 4 (128 registers, spilling) took 32 ms against 20 ms
         sh.simd_waves = 3;
+        // the gradient's registers are full: a kept bottom lives in LDS
+        sh.keep_bottom = opts().grad_keep_bottom.load() == 2;
+        sh.bottom_lds = sh.keep_bottom;
     } else {
         sh.keep_bottom = keep_bottom != 0;
         sh.bottom_lds = keep_bottom == 2;
@@ -837,11 +842,11 @@ std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
              std::to_string(sh.simd_waves) + ", " + std::to_string(sh.simd_waves) + ")))\n"
              "bat_grad_jit(bat::KParams P) {\n"
              "  __shared__ bat::LdsTables L; __shared__ bat::LdsGrad LG;\n"
-             "  bat::sweep_kernel<bat::StaticClosure<JitGraph, false>, true>(P, L, &LG);\n}\n";
+             "  bat::sweep_kernel<bat::StaticClosure<JitGraph>, true>(P, L, &LG);\n}\n";
     else if (grad)
         s += "extern \"C\" __global__ void __launch_bounds__(256) bat_grad_jit(bat::KParams P) {\n"
              "  __shared__ bat::LdsTables L; __shared__ bat::LdsGrad LG;\n"
-             "  bat::sweep_kernel<bat::StaticClosure<JitGraph, false>, true>(P, L, &LG);\n}\n";
+             "  bat::sweep_kernel<bat::StaticClosure<JitGraph>, true>(P, L, &LG);\n}\n";
     else
         s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(bat::kWave * sh.waves) + ")" +
              (sh.simd_waves ? " __attribute__((amdgpu_waves_per_eu(" + std::to_string(sh.simd_waves) + ", " +
@@ -1192,7 +1197,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     I.item_order = K.chunk_mul != 1 ? 1 : 0;
     I.block_waves = (int32_t)wpb;
     I.keep_bottom =
-        (use_jit && !rq.grad && shape.keep_bottom && P.jN <= bat::kKeepBottomMaxNodes) ? (shape.bottom_lds ? 2 : 1) : 0;
+        (use_jit && shape.keep_bottom && P.jN <= bat::kKeepBottomMaxNodes) ? (shape.bottom_lds ? 2 : 1) : 0;
     I.super_restart = (I.keep_bottom && shape.super_restart && P.jN <= kSuperMaxNodes) ? 1 : 0;
     I.window_test = use_jit ? (int32_t)K.window_test : 0;
     I.simd_waves = (use_jit && !(rq.grad && P.jN > kGradThreeWaveNodes)) ? shape.simd_waves : 0;
