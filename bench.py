@@ -42,7 +42,7 @@ PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 1.26e15 bit-ops/s
 #   valu_busy: SQ_INSTS_VALU / (256 CUs x GRBM_GUI_ACTIVE cycles);
 #   valu_insts_per_vector: SQ_INSTS_VALU x 64 lanes / 2^40 (lane-ops).
 MEASURED = {
-    "abd5bb24a8d60749/perm3/chunk12/chain3/check1/order1/waves4/super0/window1/simd6/keep1": {
+    "43a630a3f3b13d07/perm3/chunk12/chain3/check1/order1/waves4/super0/window1/simd6/keep1": {
         "traffic_bytes": (54945.3125 * 2.0 + 43996462.40625 * 1.0) * 1024,
         "valu_busy": 0.84,
         "valu_insts_per_vector": 3.58,

@@ -679,6 +679,41 @@ CacheKey cache_key(const std::string &text)
     }
     return {a, b, (uint64_t)text.size()};
 }
+// Identity of a code object's machine code: a hash of its .text and
+// .rodata sections. The rest of the object varies between compilations of
+// the same source (the compilation-unit id symbol), the code does not. A
+// blob that does not parse as a 64-bit ELF is hashed whole.
+uint64_t machine_code_id(const std::vector<char> &co)
+{
+    const size_t n = co.size();
+    auto rd = [&](size_t off, size_t len, uint64_t &v) {
+        if (off + len > n) return false;
+        v = 0;
+        for (size_t i = 0; i < len; ++i) v |= (uint64_t)(unsigned char)co[off + i] << (8 * i);
+        return true;
+    };
+    uint64_t shoff = 0, shentsize = 0, shnum = 0, shstrndx = 0;
+    const bool elf = n > 64 && co[0] == 0x7f && co[1] == 'E' && co[2] == 'L' && co[3] == 'F' && co[4] == 2 &&
+                     rd(0x28, 8, shoff) && rd(0x3A, 2, shentsize) && rd(0x3C, 2, shnum) && rd(0x3E, 2, shstrndx) &&
+                     shentsize >= 64 && shstrndx < shnum && shoff + shnum * shentsize <= n;
+    if (!elf) return cache_key(std::string(co.begin(), co.end())).h1;
+    uint64_t stroff = 0;
+    if (!rd(shoff + shstrndx * shentsize + 0x18, 8, stroff)) return cache_key(std::string(co.begin(), co.end())).h1;
+    std::string text;
+    for (uint64_t i = 0; i < shnum; ++i) {
+        const size_t h = shoff + i * shentsize;
+        uint64_t name = 0, type = 0, off = 0, size = 0;
+        if (!rd(h, 4, name) || !rd(h + 4, 4, type) || !rd(h + 0x18, 8, off) || !rd(h + 0x20, 8, size)) continue;
+        if (type == 8 || off + size > n || stroff + name >= n) continue;  // no bits in the file
+        const char *nm = co.data() + stroff + name;
+        const size_t room = n - (stroff + name);
+        if (strnlen(nm, room) == room) continue;
+        if (!strcmp(nm, ".text") || !strcmp(nm, ".rodata")) text.append(co.data() + off, size);
+    }
+    if (text.empty()) return cache_key(std::string(co.begin(), co.end())).h1;
+    return cache_key(text).h1;
+}
+
 // Identity of an ahead-of-time kernel instance: the digest of the sources
 // it was compiled from, the kernel and its node-count class.
 uint64_t aot_kernel_id(const char *kernel, int nodes, bool directed)
@@ -883,7 +918,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
     std::vector<char> code;
     // the kernel's identity: its machine code, so that edits which leave
     // the code alone (comments) keep it
-    auto code_id = [&]() { return cache_key(std::string(code.begin(), code.end())).h1; };
+    auto code_id = [&]() { return machine_code_id(code); };
     if (!cdir.empty() && cache_read(cache_path(cdir, ck), ck, code)) {
         JitEntry e;
         e.id = id = code_id();
