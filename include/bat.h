@@ -275,7 +275,8 @@ int bat_get_option(const char *key, int64_t *value);
  * sweep's launch shape, specialised vs generic kernel) on an evenly spread
  * sample of the counter range of this graph and caches the fastest choice
  * under the graph's structure; a later candidate must be at least 1%
- * faster to replace an earlier one.  Later calls on a graph of the same structure use it
+ * faster to replace an earlier one.  The gradient sweep's arc order and
+ * chain length are then tuned on their own, starting from the forward's.  Later calls on a graph of the same structure use it
  * while "BAT_AUTOTUNE" is 1.  *best_ns_per_vector (may be NULL) receives the
  * best measured time per state vector.  Results never depend on the choice
  * beyond floating-point rounding; counts never change.

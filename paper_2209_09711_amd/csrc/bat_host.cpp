@@ -1537,7 +1537,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         int clog, check, jit, perm, chain, waves = -1, super_restart = -1, simd_waves = -1, keep_bottom = -1;
     };
     constexpr double kTuneMargin = 0.01;
-    auto measure = [&](const Cand &c, double &ns) -> bool {
+    auto measure = [&](const Cand &c, double &ns, bool grad = false) -> bool {
         ns = 1e300;
         for (int rep = 0; rep < 3; ++rep) {  // the first pass warms the JIT cache
             Request tmpl{};
@@ -1556,7 +1556,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
             std::vector<double> res;
             u64 cnt = 0;
             bat_launch_info li;
-            if (run_sync(n, m, arcs, p, s, t, 0, total, false, res, cnt, &tmpl) || bat_last_launch(&li)) return false;
+            if (run_sync(n, m, arcs, p, s, t, 0, total, grad, res, cnt, &tmpl) || bat_last_launch(&li)) return false;
             if (rep > 0) ns = std::min(ns, li.kernel_ms * 1e6 / (double)li.vectors);
         }
         return true;
@@ -1626,7 +1626,33 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
         tc.keep_bottom = bc.keep_bottom;
         const std::string gk = graph_key(n, m, arcs, s, t);
         g_tune[std::to_string(D.id) + " fwd " + gk] = tc;
-        g_tune[std::to_string(D.id) + " grad " + gk] = tc;
+    }
+    // the gradient sweep: its own arc order and chain length (it keeps at
+    // most 4 chained bits, and its cost is spread differently), starting
+    // from the forward's choice; the launch shape is its own and fixed
+    {
+        Cand gb{bc.clog, bc.check, bc.jit, bc.perm, std::min(bc.chain, 4)};
+        double gbest = 1e300;
+        auto gconsider = [&](const Cand &c) {
+            double ns;
+            const bool ok = measure(c, ns, true);
+            if (verbose)
+                fprintf(stderr, "bat_autotune (gradient): chunk_log2=%d check=%d jit=%d perm=%d chain=%d -> %s %.6f ns/vector\n",
+                        c.clog, c.check, c.jit, c.perm, c.chain, ok ? "ok" : "failed", ok ? ns : 0.0);
+            if (ok && ns < gbest * (1.0 - kTuneMargin)) {
+                gbest = ns;
+                gb = c;
+            }
+        };
+        gconsider(gb);
+        if (bc.jit != 0) {
+            for (int perm : {kDefaultPerm, 0})
+                for (int k : {3, 4})
+                    if (perm != gb.perm || k != gb.chain) gconsider({bc.clog, bc.check, bc.jit, perm, k});
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        TuneChoice tc{gb.clog, gb.check, gb.jit, gb.perm, gb.chain};
+        g_tune[std::to_string(D.id) + " grad " + graph_key(n, m, arcs, s, t)] = tc;
     }
     t_err.clear();
     return BAT_OK;
