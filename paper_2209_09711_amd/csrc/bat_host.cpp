@@ -794,14 +794,17 @@ struct JitShape {
 // Default shape of the forward sweep: 4 wavefronts per block, kept block
 // bottoms, no super-block store, compiled to fit 6 wavefronts per SIMD.
 // The kernel is latency-bound: on the 5x5 grid, fitting 6 wavefronts (80
-// registers, a few spills outside the innermost loops) instead of the
-// compiler's 4 (109 registers) takes the sweep from 161 to 141 ms.
+// registers, spills outside the innermost loops) instead of the compiler's
+// 4 (109 registers) takes the sweep from 161 to 141 ms.  Plans of more
+// reach words than kDefaultSimdNodes would spill inside the sweeps at that
+// budget, so they keep the compiler's own by default.
 constexpr int kDefaultSimdWaves = 6;
+constexpr int kDefaultSimdNodes = 24;
 
 // waves: 1, 2 or 4 (anything else: 4); super_restart: 1 on, else off;
 // simd_waves: 5 to 8, 0 = the compiler's own register budget, else the
 // default; keep_bottom: 0 off, else on
-JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int keep_bottom)
+JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int keep_bottom, int nodes)
 {
     JitShape sh;
     if (grad) {
@@ -817,7 +820,9 @@ JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int 
         sh.bottom_lds = keep_bottom == 2;
         sh.waves = waves == 1 ? 1 : waves == 2 ? 2 : 4;
         sh.super_restart = super_restart == 1;
-        sh.simd_waves = (simd_waves >= 5 && simd_waves <= 8) ? simd_waves : simd_waves == 0 ? 0 : kDefaultSimdWaves;
+        sh.simd_waves = (simd_waves >= 5 && simd_waves <= 8) ? simd_waves
+                        : (simd_waves == 0 || nodes > kDefaultSimdNodes) ? 0
+                                                                         : kDefaultSimdWaves;
     }
     return sh;
 }
@@ -1189,7 +1194,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     hipFunction_t jfn = nullptr;
     double jit_ms = 0.0;
     uint64_t kernel_id = 0;
-    const JitShape shape = jit_shape(rq.grad, tc.waves, tc.super_restart, tc.simd_waves, tc.keep_bottom);
+    const JitShape shape = jit_shape(rq.grad, tc.waves, tc.super_restart, tc.simd_waves, tc.keep_bottom, P.jN);
     if (use_jit) {
         int rc = jit_get(D, P, rq.grad, shape, jfn, jit_ms, kernel_id);
         if (rc) return rc;
@@ -1499,7 +1504,7 @@ int bat_jit_source(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t
     const std::string src =
         jit_source(P, grad != 0,
                    jit_shape(grad != 0, (int)O.block_waves.load(), (int)O.super_restart.load(), (int)O.simd_waves.load(),
-                             (int)O.keep_bottom.load()));
+                             (int)O.keep_bottom.load(), P.jN));
     const uint64_t need = (uint64_t)src.size() + 1;
     const uint64_t have = *len;
     *len = need;
@@ -1605,8 +1610,9 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
     // 4-wavefront blocks wait for it)
     if (bc.jit != 0) {
         const Cand w2 = bc;
-        consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, -1, -1, 5});
-        consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, -1, -1, 0});
+        // (-1 is the default: 6, or the compiler's budget for big plans)
+        for (int sw : {5, 6, 0})
+            consider({w2.clog, w2.check, w2.jit, w2.perm, w2.chain, -1, -1, sw});
         const Cand w3 = bc;
         // the kept block bottom in LDS: no spills for it, but fewer blocks fit
         consider({w3.clog, w3.check, w3.jit, w3.perm, w3.chain, -1, -1, w3.simd_waves, 2});
