@@ -237,9 +237,7 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
  *   "BAT_SIMD_WAVES"   graph-specialised forward sweep: compile it to fit
  *                      this many wavefronts per SIMD (5..8; the compiler
  *                      then keeps fewer registers and may spill), 0 = the
- *                      compiler's own budget, -1 = tuned (else 6 for plans
- *                      of up to 24 reach words, the compiler's budget for
- *                      bigger ones)
+ *                      compiler's own budget, -1 = tuned (else 6)
  *   "BAT_KEEP_BOTTOM"  graph-specialised forward sweep: 1 = keep each
  *                      chained block's bottom closure in registers and
  *                      resume later chain starts from it, 2 = keep it in

@@ -795,11 +795,10 @@ struct JitShape {
 // bottoms, no super-block store, compiled to fit 6 wavefronts per SIMD.
 // The kernel is latency-bound: on the 5x5 grid, fitting 6 wavefronts (80
 // registers, spills outside the innermost loops) instead of the compiler's
-// 4 (109 registers) takes the sweep from 161 to 141 ms.  Plans of more
-// reach words than kDefaultSimdNodes would spill inside the sweeps at that
-// budget, so they keep the compiler's own by default.
+// 4 (109 registers) takes the sweep from 161 to 141 ms.  Bigger plans
+// spill inside the sweeps at that budget but still gained (a 29-word
+// plan: 11.6 ms against 13.5 ms with the compiler's budget).
 constexpr int kDefaultSimdWaves = 6;
-constexpr int kDefaultSimdNodes = 24;
 
 // waves: 1, 2 or 4 (anything else: 4); super_restart: 1 on, else off;
 // simd_waves: 5 to 8, 0 = the compiler's own register budget, else the
@@ -820,9 +819,8 @@ JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int 
         sh.bottom_lds = keep_bottom == 2;
         sh.waves = waves == 1 ? 1 : waves == 2 ? 2 : 4;
         sh.super_restart = super_restart == 1;
-        sh.simd_waves = (simd_waves >= 5 && simd_waves <= 8) ? simd_waves
-                        : (simd_waves == 0 || nodes > kDefaultSimdNodes) ? 0
-                                                                         : kDefaultSimdWaves;
+        (void)nodes;
+        sh.simd_waves = (simd_waves >= 5 && simd_waves <= 8) ? simd_waves : simd_waves == 0 ? 0 : kDefaultSimdWaves;
     }
     return sh;
 }
