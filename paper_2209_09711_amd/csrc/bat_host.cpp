@@ -803,7 +803,7 @@ constexpr int kDefaultSimdWaves = 6;
 // waves: 1, 2 or 4 (anything else: 4); super_restart: 1 on, else off;
 // simd_waves: 5 to 8, 0 = the compiler's own register budget, else the
 // default; keep_bottom: 0 off, else on
-JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int keep_bottom, int nodes)
+JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int keep_bottom)
 {
     JitShape sh;
     if (grad) {
@@ -819,7 +819,6 @@ JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int 
         sh.bottom_lds = keep_bottom == 2;
         sh.waves = waves == 1 ? 1 : waves == 2 ? 2 : 4;
         sh.super_restart = super_restart == 1;
-        (void)nodes;
         sh.simd_waves = (simd_waves >= 5 && simd_waves <= 8) ? simd_waves : simd_waves == 0 ? 0 : kDefaultSimdWaves;
     }
     return sh;
@@ -1192,7 +1191,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     hipFunction_t jfn = nullptr;
     double jit_ms = 0.0;
     uint64_t kernel_id = 0;
-    const JitShape shape = jit_shape(rq.grad, tc.waves, tc.super_restart, tc.simd_waves, tc.keep_bottom, P.jN);
+    const JitShape shape = jit_shape(rq.grad, tc.waves, tc.super_restart, tc.simd_waves, tc.keep_bottom);
     if (use_jit) {
         int rc = jit_get(D, P, rq.grad, shape, jfn, jit_ms, kernel_id);
         if (rc) return rc;
@@ -1502,7 +1501,7 @@ int bat_jit_source(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t
     const std::string src =
         jit_source(P, grad != 0,
                    jit_shape(grad != 0, (int)O.block_waves.load(), (int)O.super_restart.load(), (int)O.simd_waves.load(),
-                             (int)O.keep_bottom.load(), P.jN));
+                             (int)O.keep_bottom.load()));
     const uint64_t need = (uint64_t)src.size() + 1;
     const uint64_t have = *len;
     *len = need;
