@@ -534,6 +534,28 @@ def test_series_joining():
             assert out[1][1] == o.count and rel_ok(out[1][0], o.sum)
 
 
+def test_sparse_graphs_specialised_vs_oracle():
+    """Sparse random graphs (a spanning tree plus a few extra arcs: many
+    degree-2 nodes, dead ends, long series paths) through the specialised
+    kernels, whose plans join series arcs and relax one way at s and t:
+    R, counts and gradients against the oracle."""
+    B = _B()
+    rng = np.random.default_rng(424242)
+    for i in range(12):
+        n = int(rng.integers(8, 21))
+        m = min(22, n - 1 + int(rng.integers(1, 5)))
+        net = W.random_connected(n, m, seed=int(rng.integers(1 << 30)), p_lo=0.2, p_hi=0.99)
+        say("sparse", i, net.n, net.m)
+        with options(BAT_JIT=1):
+            R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+            assert B.bat_last_launch().specialised == 1
+            g = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
+        o = oracle.net_reliability(net, grad=True)
+        assert cnt == o.count == g.count and rel_ok(R, o.sum) and rel_ok(g.R, o.sum)
+        for j in range(net.m):
+            assert rel_ok(g.T1[j], o.T1[j]) and rel_ok(g.T0[j], o.T0[j]), (net.name, j)
+
+
 @pytest.mark.parametrize("order", [0, 1])
 def test_item_orders(order):
     """Counter-order and spread work-item orders sweep the same vectors: equal
