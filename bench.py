@@ -141,7 +141,7 @@ def main():
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the enumeration would shard "
-              f"by counter ranges across GPUs, which this build does not launch.", file=sys.stderr)
+              f"by counter ranges across GPUs, which this library does not launch.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

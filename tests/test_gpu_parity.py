@@ -1,6 +1,6 @@
 """GPU parity: the HIP library against the CPU oracle (and the frontier DP).
 
-Bars (from the benchmark's tolerance for the sum of up to 2^40 FP64 terms):
+Bars (the tolerance for a sum of up to 2^40 FP64 terms):
 feasible counts bit-exact; R within 1e-12 relative; T1_i and T0_i within
 1e-12 relative; dR/dp_i within 1e-12 (T1_i + T0_i) absolute.  Both kernel
 instantiations are covered: the generic one (graph read at run time) and the
