@@ -37,6 +37,11 @@
  *    _async functions: after the work queued on the stream has run).
  *  - Threads: calls are re-entrant; synchronous calls run on a per-thread
  *    stream of the current HIP device, _async calls on the stream given.
+ *  - Memory: synchronous single-graph calls reuse a device workspace and a
+ *    pinned host staging buffer kept per thread and device (grown when a
+ *    call needs more, never shrunk; an exiting thread's go to later
+ *    threads).  _async calls allocate their workspace on the given stream
+ *    and free it there.
  *  - Results are deterministic: the same inputs give bitwise the same R,
  *    count and gradient on every run (fixed-order reductions, no
  *    floating-point atomics).
