@@ -30,8 +30,9 @@
  *    [0, 1].
  *  - Limits: 2 <= n_nodes <= BAT_MAX_NODES, 0 <= n_arcs <= BAT_MAX_ARCS.
  *    m = 0 is one empty, disconnected vector: R = 0, count = 0.
- *  - Return value: BAT_OK (0) or a negative BAT_E* code.  On error the
- *    outputs are left untouched and bat_last_error() describes the failure.
+ *  - Return value: BAT_OK (0) or a negative BAT_E* code (and BAT_PENDING
+ *    from bat_reliability_checkpointed).  On error the outputs are left
+ *    untouched and bat_last_error() describes the failure.
  *  - Ownership: the caller owns every buffer.  The library copies what it
  *    needs during the call and keeps no pointer after it returns (for the
  *    _async functions: after the work queued on the stream has run).
@@ -60,6 +61,8 @@ extern "C" {
 #define BAT_ETOOBIG (-2) /* n_nodes > BAT_MAX_NODES or n_arcs > BAT_MAX_ARCS */
 #define BAT_EDEVICE (-3) /* HIP runtime or JIT compiler error; text in bat_last_error() */
 #define BAT_ENOMEM (-4)  /* host or device allocation failed */
+#define BAT_EIO (-5)     /* a checkpoint file could not be read, parsed or written */
+#define BAT_PENDING 1    /* bat_reliability_checkpointed: chunks remain (not an error) */
 
 #define BAT_MAX_NODES 64
 #define BAT_MAX_ARCS 62
@@ -138,6 +141,49 @@ int bat_reliability_range_ex(int32_t n_nodes, int32_t n_arcs, const bat_arc *arc
                              int32_t s, int32_t t, uint32_t flags, uint64_t c_lo, uint64_t c_hi,
                              double *R_hi, double *R_lo, uint64_t *count_out,
                              double *T1_out, double *T0_out);
+
+/*
+ * A whole sweep, as bat_reliability_ex, run as consecutive chunks of
+ * 2^chunk_log2 indices (chunk_log2 >= n_arcs gives one chunk; 0 <=
+ * chunk_log2 <= BAT_MAX_ARCS).
+ * Chunk j covers the indices [j 2^chunk_log2, (j+1) 2^chunk_log2), the
+ * j-th of the equal divisions of Section 4 (Eq. 6) with
+ * chi = 2^(n_arcs - chunk_log2), and goes through the range computation
+ * of bat_reliability_range_ex.  Chunks run in index order and are added
+ * in that order: R and each T1_i, T0_i as double-doubles, the count
+ * exactly.  The result therefore depends on chunk_log2 only through
+ * rounding, and not at all on how the chunks are spread over calls.
+ *
+ *   path        NULL, or a checkpoint file.  After each chunk the running
+ *               sums are written to path + ".tmp", flushed to disk and
+ *               renamed over path (readers see the old file or the new
+ *               one, whole).  A later call for the same problem resumes
+ *               after the last chunk the file holds; a finished file
+ *               returns its result without touching the device.  The file
+ *               is text: a format line, a line naming the problem (n_nodes,
+ *               n_arcs, s, t, flags, chunk_log2, whether gradient sums are
+ *               kept, 64-bit FNV-1a hashes of the arc list and of p's
+ *               bytes), the chunk count, the chunks done, the count, then R
+ *               and the per-arc T1 and T0 as hexadecimal floating-point
+ *               pairs (hi lo).  The caller owns the file; it is kept after
+ *               the sweep ends.
+ *   max_chunks  run at most this many chunks in this call (< 0: no limit),
+ *               so one call's time can be bounded.
+ *   dRdp_out, T1_out, T0_out  nullable, n_arcs doubles each; gradient sums
+ *               are kept when any is set (and are part of the problem).
+ *
+ * Returns BAT_OK with every output set once all chunks are done, or
+ * BAT_PENDING with the outputs untouched while chunks remain.  A file
+ * naming another problem is BAT_EINVAL and is left as it is; a file that
+ * cannot be read, parsed or replaced is BAT_EIO.  Other errors as for
+ * bat_reliability_range_ex; the file then holds the chunks finished before
+ * the failing one.  Two calls must not share one file at the same time.
+ */
+int bat_reliability_checkpointed(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const double *p,
+                                 int32_t s, int32_t t, uint32_t flags, int32_t chunk_log2,
+                                 const char *path, int64_t max_chunks,
+                                 double *R_out, uint64_t *count_out,
+                                 double *dRdp_out, double *T1_out, double *T0_out);
 
 /*
  * Many networks, many probability vectors, one persistent launch.

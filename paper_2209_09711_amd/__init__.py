@@ -23,6 +23,8 @@ BAT_EINVAL = -1
 BAT_ETOOBIG = -2
 BAT_EDEVICE = -3
 BAT_ENOMEM = -4
+BAT_EIO = -5
+BAT_PENDING = 1
 BAT_MAX_NODES = 64
 BAT_MAX_ARCS = 62
 BAT_MAX_PVEC = 1024
@@ -32,7 +34,7 @@ EXPORTED = ("bat_version", "bat_last_error", "bat_reliability", "bat_reliability
             "bat_reliability_range", "bat_reliability_batched", "bat_reliability_async",
             "bat_reliability_grad_async", "bat_set_option", "bat_get_option", "bat_autotune",
             "bat_last_launch", "bat_jit_source", "bat_autotune_batched", "bat_reliability_ex",
-            "bat_reliability_range_ex")
+            "bat_reliability_range_ex", "bat_reliability_checkpointed")
 
 
 class bat_arc(ctypes.Structure):
@@ -87,6 +89,8 @@ def _load():
         "bat_reliability_ex": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, P, P, P, P, P], ctypes.c_int),
         "bat_reliability_range_ex": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, u64, u64, P, P, P, P, P],
                                      ctypes.c_int),
+        "bat_reliability_checkpointed": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, i32, ctypes.c_char_p, i64,
+                                          P, P, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -225,6 +229,32 @@ def bat_reliability_ex(n_nodes: int, arcs, p, s: int, t: int, directed: bool = F
     T0 = np.zeros(max(m, 1)) if grad else None
     _check(_lib.bat_reliability_ex(n_nodes, m, _ptr(a), _ptr(pv), s, t, _flags(directed), ctypes.byref(R),
                                    ctypes.byref(cnt), _ptr(g), _ptr(T1), _ptr(T0)))
+    if not grad:
+        return R.value, cnt.value
+    return GradResult(R.value, cnt.value, g[:m], T1[:m], T0[:m])
+
+
+def bat_reliability_checkpointed(n_nodes: int, arcs, p, s: int, t: int, chunk_log2: int, path=None,
+                                 max_chunks: int = -1, grad: bool = False, directed: bool = False,
+                                 forward: bool = False):
+    """A whole sweep run as chunks of 2^chunk_log2 indices, with the running
+    sums kept in the checkpoint file `path` (None: no file).  Returns None
+    while chunks remain (BAT_PENDING), else (R, count) or a GradResult."""
+    a = _arcs(arcs)
+    m = a.shape[0]
+    pv = _p(p, m)
+    R = ctypes.c_double(0.0)
+    cnt = ctypes.c_uint64(0)
+    g = np.zeros(max(m, 1)) if grad else None
+    T1 = np.zeros(max(m, 1)) if grad else None
+    T0 = np.zeros(max(m, 1)) if grad else None
+    rc = _lib.bat_reliability_checkpointed(n_nodes, m, _ptr(a), _ptr(pv), s, t, _flags(directed, forward),
+                                           int(chunk_log2), None if path is None else os.fsencode(path),
+                                           int(max_chunks), ctypes.byref(R), ctypes.byref(cnt), _ptr(g), _ptr(T1),
+                                           _ptr(T0))
+    if rc == BAT_PENDING:
+        return None
+    _check(rc)
     if not grad:
         return R.value, cnt.value
     return GradResult(R.value, cnt.value, g[:m], T1[:m], T0[:m])

@@ -16,6 +16,7 @@
 #include <hip/hiprtc.h>
 
 #include <atomic>
+#include <cerrno>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -1320,6 +1321,144 @@ void split_grad(const std::vector<double> &res, const std::vector<int> &cb_of_ar
     }
 }
 
+// ------------------------------------------------------------ checkpoints
+// A chunked sweep's running sums: R and the per-arc T1 / T0 as unevaluated
+// double-doubles (hi, lo), the count exactly.
+struct RunningSums {
+    u64 done = 0;
+    u64 count = 0;
+    double R[2] = {0.0, 0.0};
+    std::vector<double> T1, T0;  // 2 m each (hi, lo per arc) when kept
+};
+
+// hi + lo += x_hi + x_lo (Knuth's two-sum on the high parts)
+void dd_acc(double *d, double x_hi, double x_lo)
+{
+    const double s = d[0] + x_hi;
+    const double bb = s - d[0];
+    const double e = (d[0] - (s - bb)) + (x_hi - bb);
+    const double lo = e + d[1] + x_lo;
+    d[0] = s + lo;
+    d[1] = lo - (d[0] - s);
+}
+
+uint64_t fnv_bytes(uint64_t h, const void *data, size_t len)
+{
+    const unsigned char *b = (const unsigned char *)data;
+    for (size_t i = 0; i < len; ++i) h = (h ^ b[i]) * 1099511628211ull;  // FNV-1a
+    return h;
+}
+
+// The line that names the problem a checkpoint file belongs to.
+std::string checkpoint_problem(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                               uint32_t flags, int32_t clog, bool grad)
+{
+    uint64_t ha = fnv_bytes(1469598103934665603ull, arcs, sizeof(bat_arc) * (size_t)m);
+    uint64_t hp = fnv_bytes(1469598103934665603ull, p, sizeof(double) * (size_t)m);
+    char buf[256];
+    snprintf(buf, sizeof buf, "problem n=%d m=%d s=%d t=%d flags=%u chunk_log2=%d grad=%d arcs=%016llx p=%016llx",
+             n, m, s, t, flags, clog, grad ? 1 : 0, (unsigned long long)ha, (unsigned long long)hp);
+    return buf;
+}
+
+const char *kCheckpointMagic = "bat-checkpoint 1";
+
+// Reads `path` into S.  1: no such file (a fresh start), 0: read, < 0: error.
+int checkpoint_read(const char *path, const std::string &problem, u64 chunks, bool grad, int32_t m, RunningSums &S)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) {
+        if (errno == ENOENT) return 1;
+        return fail(BAT_EIO, "checkpoint %s: cannot open (%s)", path, strerror(errno));
+    }
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    const bool bad_read = ferror(f) != 0;
+    fclose(f);
+    if (bad_read) return fail(BAT_EIO, "checkpoint %s: read error", path);
+    std::vector<std::string> lines;
+    for (size_t a = 0, b; a < text.size(); a = b + 1) {
+        b = text.find('\n', a);
+        if (b == std::string::npos) b = text.size();
+        lines.push_back(text.substr(a, b - a));
+    }
+    if (lines.size() < 2 || lines[0] != kCheckpointMagic)
+        return fail(BAT_EIO, "checkpoint %s: not a checkpoint file", path);
+    if (lines[1] != problem)
+        return fail(BAT_EINVAL, "checkpoint %s belongs to another problem (%s; this call: %s)", path,
+                    lines[1].c_str(), problem.c_str());
+    if (lines.size() < (grad ? 8u : 6u)) return fail(BAT_EIO, "checkpoint %s: truncated", path);
+    unsigned long long total = 0, done = 0, cnt = 0;
+    char tail;
+    if (sscanf(lines[2].c_str(), "chunks %llu %c", &total, &tail) != 1 || total != chunks ||
+        sscanf(lines[3].c_str(), "done %llu %c", &done, &tail) != 1 || done > total ||
+        sscanf(lines[4].c_str(), "count %llu %c", &cnt, &tail) != 1)
+        return fail(BAT_EIO, "checkpoint %s: malformed header", path);
+    // "<tag> hi lo [hi lo ...]" with hexadecimal floats (exact round trip)
+    auto doubles = [&](const std::string &ln, const char *tag, size_t want, double *out) {
+        const size_t tl = strlen(tag);
+        if (ln.compare(0, tl, tag) != 0) return false;
+        const char *q = ln.c_str() + tl;
+        for (size_t i = 0; i < want; ++i) {
+            char *e = nullptr;
+            out[i] = strtod(q, &e);
+            if (e == q || !std::isfinite(out[i])) return false;
+            q = e;
+        }
+        while (*q == ' ') ++q;
+        return *q == '\0';
+    };
+    RunningSums R;
+    R.done = done;
+    R.count = cnt;
+    if (!doubles(lines[5], "R", 2, R.R)) return fail(BAT_EIO, "checkpoint %s: malformed R line", path);
+    if (grad) {
+        R.T1.assign(2 * (size_t)m, 0.0);
+        R.T0.assign(2 * (size_t)m, 0.0);
+        if (!doubles(lines[6], "T1", 2 * (size_t)m, R.T1.data()) || !doubles(lines[7], "T0", 2 * (size_t)m, R.T0.data()))
+            return fail(BAT_EIO, "checkpoint %s: malformed T1/T0 lines", path);
+    }
+    S = std::move(R);
+    return 0;
+}
+
+// Writes S to path + ".tmp", then renames it over `path`, so a reader sees
+// either the old file or the new one whole.
+int checkpoint_write(const char *path, const std::string &problem, u64 chunks, bool grad, const RunningSums &S)
+{
+    std::string text = std::string(kCheckpointMagic) + "\n" + problem + "\n";
+    char buf[128];
+    snprintf(buf, sizeof buf, "chunks %llu\ndone %llu\ncount %llu\nR %a %a\n", (unsigned long long)chunks,
+             (unsigned long long)S.done, (unsigned long long)S.count, S.R[0], S.R[1]);
+    text += buf;
+    if (grad) {
+        for (int w = 0; w < 2; ++w) {
+            const std::vector<double> &v = w ? S.T0 : S.T1;
+            text += w ? "T0" : "T1";
+            for (double x : v) {
+                snprintf(buf, sizeof buf, " %a", x);
+                text += buf;
+            }
+            text += "\n";
+        }
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return fail(BAT_EIO, "checkpoint %s: cannot create (%s)", tmp.c_str(), strerror(errno));
+    const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size() && fflush(f) == 0 && fsync(fileno(f)) == 0;
+    if (fclose(f) != 0 || !ok) {
+        unlink(tmp.c_str());
+        return fail(BAT_EIO, "checkpoint %s: write failed", tmp.c_str());
+    }
+    if (rename(tmp.c_str(), path) != 0) {
+        unlink(tmp.c_str());
+        return fail(BAT_EIO, "checkpoint %s: rename failed (%s)", path, strerror(errno));
+    }
+    return BAT_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1428,6 +1567,64 @@ int bat_reliability_range(int32_t n, int32_t m, const bat_arc *arcs, const doubl
                           double *T1_out, double *T0_out)
 {
     return bat_reliability_range_ex(n, m, arcs, p, s, t, 0u, c_lo, c_hi, R_hi, R_lo, count_out, T1_out, T0_out);
+}
+
+int bat_reliability_checkpointed(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                                 uint32_t flags, int32_t chunk_log2, const char *path, int64_t max_chunks,
+                                 double *R_out, uint64_t *count_out, double *dRdp_out, double *T1_out,
+                                 double *T0_out)
+{
+    t_err.clear();
+    if (!R_out || !count_out) return fail(BAT_EINVAL, "NULL output pointer");
+    if (flags & ~(uint32_t)(BAT_DIRECTED | BAT_FORWARD_ORDER)) return fail(BAT_EINVAL, "unknown flags 0x%x", flags);
+    if (chunk_log2 < 0 || chunk_log2 > BAT_MAX_ARCS)
+        return fail(BAT_EINVAL, "chunk_log2 %d outside [0, %d]", chunk_log2, BAT_MAX_ARCS);
+    if (!p && m > 0) return fail(BAT_EINVAL, "p is NULL");
+    int rc = validate(n, m, arcs, p, s, t);
+    if (rc) return rc;
+    const bool grad = dRdp_out || T1_out || T0_out;
+    const int32_t clog = chunk_log2 < m ? chunk_log2 : m;
+    const u64 chunks = 1ull << (m - clog);
+    const std::string problem = checkpoint_problem(n, m, arcs, p, s, t, flags, chunk_log2, grad);
+    RunningSums S;
+    if (grad) {
+        S.T1.assign(2 * (size_t)m, 0.0);
+        S.T0.assign(2 * (size_t)m, 0.0);
+    }
+    if (path) {
+        rc = checkpoint_read(path, problem, chunks, grad, m, S);
+        if (rc < 0) return rc;
+    }
+    std::vector<double> t1(m > 0 ? m : 1), t0(m > 0 ? m : 1);
+    for (int64_t ran = 0; S.done < chunks && (max_chunks < 0 || ran < max_chunks); ++ran) {
+        const u64 lo = S.done << clog, hi = (S.done + 1) << clog;
+        double h = 0.0, l = 0.0;
+        uint64_t c = 0;
+        rc = bat_reliability_range_ex(n, m, arcs, p, s, t, flags, lo, hi, &h, &l, &c, grad ? t1.data() : nullptr,
+                                      grad ? t0.data() : nullptr);
+        if (rc) return rc;
+        dd_acc(S.R, h, l);
+        S.count += c;
+        for (int32_t a = 0; grad && a < m; ++a) {
+            dd_acc(&S.T1[2 * a], t1[a], 0.0);
+            dd_acc(&S.T0[2 * a], t0[a], 0.0);
+        }
+        ++S.done;
+        if (path) {
+            rc = checkpoint_write(path, problem, chunks, grad, S);
+            if (rc) return rc;
+        }
+    }
+    if (S.done < chunks) return BAT_PENDING;
+    *R_out = S.R[0] + S.R[1];
+    *count_out = S.count;
+    for (int32_t a = 0; grad && a < m; ++a) {
+        const double *a1 = &S.T1[2 * a], *a0 = &S.T0[2 * a];
+        if (dRdp_out) dRdp_out[a] = (a1[0] - a0[0]) + (a1[1] - a0[1]);
+        if (T1_out) T1_out[a] = a1[0] + a1[1];
+        if (T0_out) T0_out[a] = a0[0] + a0[1];
+    }
+    return BAT_OK;
 }
 
 static int async_common(int32_t n, int32_t m, const bat_arc *arcs, const double *p_dev, int32_t s, int32_t t,

@@ -188,7 +188,7 @@ def test_header_is_plain_c(tmp_path):
     src += [f"    (fp){n}," for n in names]
     src += ["};", "size_t n_table = sizeof table / sizeof table[0];",
             "int check(void) { bat_arc a = {0, 1}; return a.u + a.v + BAT_OK + BAT_EINVAL + BAT_ETOOBIG"
-            " + BAT_EDEVICE + BAT_ENOMEM + BAT_MAX_NODES + BAT_MAX_ARCS + BAT_MAX_PVEC + (int)BAT_DIRECTED"
+            " + BAT_EDEVICE + BAT_ENOMEM + BAT_EIO + BAT_PENDING + BAT_MAX_NODES + BAT_MAX_ARCS + BAT_MAX_PVEC + (int)BAT_DIRECTED"
             " + (int)BAT_FORWARD_ORDER; }"]
     f = tmp_path / "abi.c"
     f.write_text("\n".join(src) + "\n")
