@@ -143,15 +143,22 @@ int bat_reliability_range_ex(int32_t n_nodes, int32_t n_arcs, const bat_arc *arc
                              double *T1_out, double *T0_out);
 
 /*
- * A whole sweep, as bat_reliability_ex, run as consecutive chunks of
- * 2^chunk_log2 indices (chunk_log2 >= n_arcs gives one chunk; 0 <=
- * chunk_log2 <= BAT_MAX_ARCS).
- * Chunk j covers the indices [j 2^chunk_log2, (j+1) 2^chunk_log2), the
- * j-th of the equal divisions of Section 4 (Eq. 6) with
- * chi = 2^(n_arcs - chunk_log2), and goes through the range computation
- * of bat_reliability_range_ex.  Chunks run in index order and are added
- * in that order: R and each T1_i, T0_i as double-doubles, the count
- * exactly.  The result therefore depends on chunk_log2 only through
+ * A whole sweep, as bat_reliability_ex, run in chunks of about
+ * 2^chunk_log2 vectors each (0 <= chunk_log2 <= BAT_MAX_ARCS; chunk_log2 >=
+ * n_arcs gives one chunk), each chunk one call's worth of work.  The whole
+ * sweep's work items (blocks of the counter, the way a single call would
+ * cut it) are dealt out into J = 2^(n_arcs - chunk_log2) parts (fewer if
+ * the sweep has fewer work items): part j holds the blocks whose index is
+ * j modulo J.  So every chunk spans the whole counter, with the same mix
+ * of cheap and costly regions as a whole sweep, and runs about as fast per
+ * vector.  Contiguous divisions (Eq. 6 of Section 4, as
+ * bat_reliability_range computes them) are not used here.  The arc-to-bit
+ * order, the work-item size and the chain length are those the whole
+ * sweep would take (tuned, else the defaults; with BAT_FORWARD_ORDER, the
+ * forward BAT order of Section 4.2).  The first chunk fixes them, and the
+ * checkpoint file keeps them, so a resumed sweep uses them too.  Chunks
+ * are added in order: R and each T1_i, T0_i as double-doubles, the count
+ * exactly.  The result therefore depends on that launch only through
  * rounding, and not at all on how the chunks are spread over calls.
  *
  *   path        NULL, or a checkpoint file.  After each chunk the running
@@ -163,21 +170,24 @@ int bat_reliability_range_ex(int32_t n_nodes, int32_t n_arcs, const bat_arc *arc
  *               is text: a format line, a line naming the problem (n_nodes,
  *               n_arcs, s, t, flags, chunk_log2, whether gradient sums are
  *               kept, 64-bit FNV-1a hashes of the arc list and of p's
- *               bytes), the chunk count, the chunks done, the count, then R
- *               and the per-arc T1 and T0 as hexadecimal floating-point
- *               pairs (hi lo).  The caller owns the file; it is kept after
- *               the sweep ends.
+ *               bytes), the part count, the launch (arc order kind,
+ *               work-item size and chain length as bat_last_launch reports
+ *               them), the parts done, the count, then R and the per-arc T1
+ *               and T0 as hexadecimal floating-point pairs (hi lo).
+ *               The caller owns the file; it is kept after the sweep
+ *               ends.
  *   max_chunks  run at most this many chunks in this call (< 0: no limit),
  *               so one call's time can be bounded.
  *   dRdp_out, T1_out, T0_out  nullable, n_arcs doubles each; gradient sums
  *               are kept when any is set (and are part of the problem).
  *
  * Returns BAT_OK with every output set once all chunks are done, or
- * BAT_PENDING with the outputs untouched while chunks remain.  A file
- * naming another problem is BAT_EINVAL and is left as it is; a file that
- * cannot be read, parsed or replaced is BAT_EIO.  Other errors as for
- * bat_reliability_range_ex; the file then holds the chunks finished before
- * the failing one.  Two calls must not share one file at the same time.
+ * BAT_PENDING with the outputs untouched while chunks remain (or when no
+ * file exists and max_chunks is 0: nothing has run).  A file naming
+ * another problem is BAT_EINVAL and is left as it is; a file that cannot be
+ * read, parsed or replaced is BAT_EIO.  Other errors as for
+ * bat_reliability_ex; the file then holds the chunks finished before the
+ * failing one.  Two calls must not share one file at the same time.
  */
 int bat_reliability_checkpointed(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const double *p,
                                  int32_t s, int32_t t, uint32_t flags, int32_t chunk_log2,

@@ -995,6 +995,12 @@ struct Request {
     // timing sample (autotuner): sweep only this many work items, spread
     // over the whole counter by an odd multiplier (0 = everything)
     u64 sample_items = 0;
+    // a part of the counter, or the first part of a split sweep: work items
+    // no larger than the ~64-per-CU size
+    bool fill = false;
+    // one part of a whole sweep split into split_parts (a power of two):
+    // part split_index (0 = no split)
+    u64 split_parts = 0, split_index = 0;
 };
 
 // Options, then the tuned choice for this graph (if any and enabled), then
@@ -1073,12 +1079,19 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     const u64 g_end = g_last | bmask;
     const u64 iters = g_end - g_base + 1;
 
+    // aim at ~64 work items per CU, at most 4096 iterations each; ~256 per
+    // CU in each part of a split sweep, whose launches are short enough for
+    // their last, partly idle round of work items to matter (measured on
+    // the 40-arc grid in 16 parts: 154 ms at 64 per CU, 127 ms at 256, 118
+    // ms unsplit)
+    const u64 per_cu = rq.split_parts ? 256ull * rq.split_parts : 64ull;
+    const u64 target = iters / ((u64)std::max(D.cus, 1) * per_cu);
+    int clog_fill = 0;
+    while (clog_fill < 12 && (2ull << clog_fill) <= target) ++clog_fill;
     int clog = tc.chunk_log2;
-    if (clog <= 0) {  // aim at ~64 work items per CU, at most 4096 iterations each
-        u64 target = iters / ((u64)std::max(D.cus, 1) * 64ull);
-        clog = 0;
-        while (clog < 12 && (2ull << clog) <= target) ++clog;
-    }
+    // a size tuned for the whole counter would leave a short range's last
+    // round of work items mostly idle
+    if (clog <= 0 || (rq.fill && clog > clog_fill)) clog = clog_fill;
     clog = std::min(clog, 20);
     if (chain) clog = std::max(clog, (int)ck);
     u32 f = (u32)std::max<int64_t>(0, std::min<int64_t>(O.seg_log2.load(), bat::kMaxSegLog));
@@ -1106,6 +1119,23 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
         K.chunk_mul = 0x9E3779B97F4A7C15ull;
         K.chunk_mask = K.n_chunks - 1;
         if (sample) K.n_chunks = rq.sample_items;
+    }
+    if (rq.split_parts) {
+        // Part j of J: the work items whose blocks are j modulo J, visited
+        // in spread order (item i sweeps block j + J ((i M) mod S), S = N / J
+        // items per part), so every part samples the whole counter the way
+        // a whole sweep does.  min(J, N) parts.
+        const u64 N = K.n_chunks;
+        if (!pow2 || sample || (rq.split_parts & (rq.split_parts - 1)))
+            return fail(BAT_EINVAL, "cannot split %llu work items into %llu parts", (unsigned long long)N,
+                        (unsigned long long)rq.split_parts);
+        const u64 parts = std::min<u64>(rq.split_parts, N);
+        if (rq.split_index >= parts)
+            return fail(BAT_EINVAL, "part %llu of %llu", (unsigned long long)rq.split_index, (unsigned long long)parts);
+        K.g_base = g_base + rq.split_index * K.chunk_iters;
+        K.chunk_mul = 0x9E3779B97F4A7C15ull * parts;
+        K.chunk_mask = N - 1;
+        K.n_chunks = N / parts;
     }
     K.m = m;
     K.ubits = ubits;
@@ -1321,10 +1351,63 @@ void split_grad(const std::vector<double> &res, const std::vector<int> &cb_of_ar
     }
 }
 
+// Partial sums over [c_lo, c_hi) of the counter whose bits follow arc-to-bit
+// order kind `perm` (0: the paper's backward BAT indices, kPermForward: its
+// forward ones); arguments already validated except the probabilities.
+int range_in_order(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
+                   uint32_t flags, int perm, u64 c_lo, u64 c_hi, double *R_hi, double *R_lo, uint64_t *count_out,
+                   double *T1_out, double *T0_out)
+{
+    const bool grad = T1_out != nullptr;
+    if (c_lo == c_hi) {
+        int rc = validate(n, m, arcs, p, s, t);
+        if (rc) return rc;
+        *R_hi = *R_lo = 0.0;
+        *count_out = 0;
+        if (grad)
+            for (int32_t a = 0; a < m; ++a) T1_out[a] = T0_out[a] = 0.0;
+        return BAT_OK;
+    }
+    std::vector<double> res;
+    std::vector<int> cba;
+    u64 cnt = 0;
+    Request order{};
+    order.force_perm = perm;
+    order.fill = true;
+    int rc = run_sync(n, m, arcs, p, s, t, c_lo, c_hi, grad, res, cnt, &order, &cba, flags);
+    if (rc) return rc;
+    *R_hi = res[0];
+    *R_lo = res[1];
+    *count_out = cnt;
+    if (grad) split_grad(res, cba, m, nullptr, T1_out, T0_out);
+    return BAT_OK;
+}
+
+// The arc-to-bit order a whole sweep of this graph would take (tuned or
+// default); the forward BAT order when the flags ask for it.
+int whole_sweep_order(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t t, uint32_t flags, bool grad,
+                      int &perm)
+{
+    if (flags & BAT_FORWARD_ORDER) {
+        perm = kPermForward;
+        return BAT_OK;
+    }
+    DeviceInfo D;
+    int rc = current_device(D);
+    if (rc) return rc;
+    const TuneChoice tc = choose(D, graph_key(n, m, arcs, s, t, (flags & BAT_DIRECTED) != 0), grad, nullptr);
+    perm = tc.perm >= 0 && tc.perm < kPermKinds ? tc.perm : kDefaultPerm;
+    return BAT_OK;
+}
+
 // ------------------------------------------------------------ checkpoints
 // A chunked sweep's running sums: R and the per-arc T1 / T0 as unevaluated
 // double-doubles (hi, lo), the count exactly.
 struct RunningSums {
+    // the launch every chunk repeats (-1: no chunk run yet): arc-to-bit
+    // order kind, work-item size (log2 iterations), chain length
+    int order = -1, items = -1, chain = -1;
+    u64 parts = 0;  // chunks: parts of the whole sweep's work items
     u64 done = 0;
     u64 count = 0;
     double R[2] = {0.0, 0.0};
@@ -1364,7 +1447,8 @@ std::string checkpoint_problem(int32_t n, int32_t m, const bat_arc *arcs, const 
 const char *kCheckpointMagic = "bat-checkpoint 1";
 
 // Reads `path` into S.  1: no such file (a fresh start), 0: read, < 0: error.
-int checkpoint_read(const char *path, const std::string &problem, u64 chunks, bool grad, int32_t m, RunningSums &S)
+int checkpoint_read(const char *path, const std::string &problem, bool grad, int32_t m, uint32_t flags,
+                    RunningSums &S)
 {
     FILE *f = fopen(path, "r");
     if (!f) {
@@ -1389,13 +1473,22 @@ int checkpoint_read(const char *path, const std::string &problem, u64 chunks, bo
     if (lines[1] != problem)
         return fail(BAT_EINVAL, "checkpoint %s belongs to another problem (%s; this call: %s)", path,
                     lines[1].c_str(), problem.c_str());
-    if (lines.size() < (grad ? 8u : 6u)) return fail(BAT_EIO, "checkpoint %s: truncated", path);
-    unsigned long long total = 0, done = 0, cnt = 0;
+    if (lines.size() < (grad ? 9u : 7u)) return fail(BAT_EIO, "checkpoint %s: truncated", path);
+    unsigned long long parts = 0, done = 0, cnt = 0;
+    int order = -1, items = -1, chain = -1;
     char tail;
-    if (sscanf(lines[2].c_str(), "chunks %llu %c", &total, &tail) != 1 || total != chunks ||
-        sscanf(lines[3].c_str(), "done %llu %c", &done, &tail) != 1 || done > total ||
-        sscanf(lines[4].c_str(), "count %llu %c", &cnt, &tail) != 1)
+    if (sscanf(lines[2].c_str(), "parts %llu %c", &parts, &tail) != 1 ||
+        sscanf(lines[3].c_str(), "launch order=%d items=%d chain=%d %c", &order, &items, &chain, &tail) != 3 ||
+        sscanf(lines[4].c_str(), "done %llu %c", &done, &tail) != 1 ||
+        sscanf(lines[5].c_str(), "count %llu %c", &cnt, &tail) != 1)
         return fail(BAT_EIO, "checkpoint %s: malformed header", path);
+    const int ubits = m > bat::kWordBits ? m - bat::kWordBits : 0;
+    const bool fwd = (flags & BAT_FORWARD_ORDER) != 0;
+    if (fwd ? order != kPermForward : (order < 0 || order >= kPermKinds))
+        return fail(BAT_EIO, "checkpoint %s: bad arc order %d", path, order);
+    if (items < 0 || items > 20 || (chain != 0 && (chain < 3 || chain > 6)) || parts == 0 ||
+        (parts & (parts - 1)) != 0 || parts > (1ull << std::max(ubits - items, 0)) || done > parts)
+        return fail(BAT_EIO, "checkpoint %s: bad launch or part counts", path);
     // "<tag> hi lo [hi lo ...]" with hexadecimal floats (exact round trip)
     auto doubles = [&](const std::string &ln, const char *tag, size_t want, double *out) {
         const size_t tl = strlen(tag);
@@ -1411,13 +1504,17 @@ int checkpoint_read(const char *path, const std::string &problem, u64 chunks, bo
         return *q == '\0';
     };
     RunningSums R;
+    R.order = order;
+    R.items = items;
+    R.chain = chain;
+    R.parts = parts;
     R.done = done;
     R.count = cnt;
-    if (!doubles(lines[5], "R", 2, R.R)) return fail(BAT_EIO, "checkpoint %s: malformed R line", path);
+    if (!doubles(lines[6], "R", 2, R.R)) return fail(BAT_EIO, "checkpoint %s: malformed R line", path);
     if (grad) {
         R.T1.assign(2 * (size_t)m, 0.0);
         R.T0.assign(2 * (size_t)m, 0.0);
-        if (!doubles(lines[6], "T1", 2 * (size_t)m, R.T1.data()) || !doubles(lines[7], "T0", 2 * (size_t)m, R.T0.data()))
+        if (!doubles(lines[7], "T1", 2 * (size_t)m, R.T1.data()) || !doubles(lines[8], "T0", 2 * (size_t)m, R.T0.data()))
             return fail(BAT_EIO, "checkpoint %s: malformed T1/T0 lines", path);
     }
     S = std::move(R);
@@ -1426,12 +1523,13 @@ int checkpoint_read(const char *path, const std::string &problem, u64 chunks, bo
 
 // Writes S to path + ".tmp", then renames it over `path`, so a reader sees
 // either the old file or the new one whole.
-int checkpoint_write(const char *path, const std::string &problem, u64 chunks, bool grad, const RunningSums &S)
+int checkpoint_write(const char *path, const std::string &problem, bool grad, const RunningSums &S)
 {
     std::string text = std::string(kCheckpointMagic) + "\n" + problem + "\n";
     char buf[128];
-    snprintf(buf, sizeof buf, "chunks %llu\ndone %llu\ncount %llu\nR %a %a\n", (unsigned long long)chunks,
-             (unsigned long long)S.done, (unsigned long long)S.count, S.R[0], S.R[1]);
+    snprintf(buf, sizeof buf, "parts %llu\nlaunch order=%d items=%d chain=%d\ndone %llu\ncount %llu\nR %a %a\n",
+             (unsigned long long)S.parts, S.order, S.items, S.chain, (unsigned long long)S.done,
+             (unsigned long long)S.count, S.R[0], S.R[1]);
     text += buf;
     if (grad) {
         for (int w = 0; w < 2; ++w) {
@@ -1456,6 +1554,47 @@ int checkpoint_write(const char *path, const std::string &problem, u64 chunks, b
         unlink(tmp.c_str());
         return fail(BAT_EIO, "checkpoint %s: rename failed (%s)", path, strerror(errno));
     }
+    return BAT_OK;
+}
+
+// Chunk S.done of a checkpointed sweep: one part of the whole sweep's work
+// items (queue_sweep's split), under the launch the first chunk took: its
+// arc order, work-item size and chain length fix which blocks each part
+// holds and how its sums are rounded.
+int run_part(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t, uint32_t flags,
+             bool grad, u64 parts_wanted, RunningSums &S, double *R_hl, uint64_t *count, double *T1, double *T0)
+{
+    Request rq{};
+    const bool first = S.order < 0;
+    if (first) {
+        int rc = whole_sweep_order(n, m, arcs, s, t, flags, grad, rq.force_perm);
+        if (rc) return rc;
+        rq.split_parts = parts_wanted;
+        rq.fill = true;
+    } else {
+        rq.force_perm = S.order;
+        rq.force_chunk_log2 = S.items;
+        rq.force_chain = S.chain;
+        rq.split_parts = S.parts;
+    }
+    rq.split_index = S.done;
+    std::vector<double> res;
+    std::vector<int> cba;
+    u64 cnt = 0;
+    int rc = run_sync(n, m, arcs, p, s, t, 0, 1ull << m, grad, res, cnt, &rq, &cba, flags);
+    if (rc) return rc;
+    if (first) {
+        const bat_launch_info &I = t_state.info;
+        const int ubits = m > bat::kWordBits ? m - bat::kWordBits : 0;
+        S.order = I.perm;
+        S.items = I.chunk_log2;
+        S.chain = I.chain_log2;
+        S.parts = std::min<u64>(parts_wanted, 1ull << std::max(ubits - S.items, 0));
+    }
+    R_hl[0] = res[0];
+    R_hl[1] = res[1];
+    *count = cnt;
+    if (grad) split_grad(res, cba, m, nullptr, T1, T0);
     return BAT_OK;
 }
 
@@ -1537,29 +1676,9 @@ int bat_reliability_range_ex(int32_t n, int32_t m, const bat_arc *arcs, const do
     if (m < 0 || m > BAT_MAX_ARCS) return validate(n, m, arcs, p, s, t);
     if (c_lo > c_hi || c_hi > (1ull << m)) return fail(BAT_EINVAL, "bad range [%llu, %llu) for m = %d",
                                                      (unsigned long long)c_lo, (unsigned long long)c_hi, m);
-    bool grad = T1_out != nullptr;
-    if (c_lo == c_hi) {
-        int rc = validate(n, m, arcs, p, s, t);
-        if (rc) return rc;
-        *R_hi = *R_lo = 0.0;
-        *count_out = 0;
-        if (grad)
-            for (int32_t a = 0; a < m; ++a) T1_out[a] = T0_out[a] = 0.0;
-        return BAT_OK;
-    }
-    std::vector<double> res;
-    std::vector<int> cba;
-    u64 cnt = 0;
-    Request order{};
     // the indices are the paper's: backward BAT (Eq. 2-3) or forward (Eq. 4-5)
-    order.force_perm = (flags & BAT_FORWARD_ORDER) ? kPermForward : 0;
-    int rc = run_sync(n, m, arcs, p, s, t, c_lo, c_hi, grad, res, cnt, &order, &cba, flags);
-    if (rc) return rc;
-    *R_hi = res[0];
-    *R_lo = res[1];
-    *count_out = cnt;
-    if (grad) split_grad(res, cba, m, nullptr, T1_out, T0_out);
-    return BAT_OK;
+    return range_in_order(n, m, arcs, p, s, t, flags, (flags & BAT_FORWARD_ORDER) ? kPermForward : 0, c_lo, c_hi,
+                          R_hi, R_lo, count_out, T1_out, T0_out);
 }
 
 int bat_reliability_range(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t s, int32_t t,
@@ -1584,7 +1703,7 @@ int bat_reliability_checkpointed(int32_t n, int32_t m, const bat_arc *arcs, cons
     if (rc) return rc;
     const bool grad = dRdp_out || T1_out || T0_out;
     const int32_t clog = chunk_log2 < m ? chunk_log2 : m;
-    const u64 chunks = 1ull << (m - clog);
+    const u64 parts_wanted = 1ull << (m - clog);
     const std::string problem = checkpoint_problem(n, m, arcs, p, s, t, flags, chunk_log2, grad);
     RunningSums S;
     if (grad) {
@@ -1592,18 +1711,17 @@ int bat_reliability_checkpointed(int32_t n, int32_t m, const bat_arc *arcs, cons
         S.T0.assign(2 * (size_t)m, 0.0);
     }
     if (path) {
-        rc = checkpoint_read(path, problem, chunks, grad, m, S);
+        rc = checkpoint_read(path, problem, grad, m, flags, S);
         if (rc < 0) return rc;
     }
     std::vector<double> t1(m > 0 ? m : 1), t0(m > 0 ? m : 1);
-    for (int64_t ran = 0; S.done < chunks && (max_chunks < 0 || ran < max_chunks); ++ran) {
-        const u64 lo = S.done << clog, hi = (S.done + 1) << clog;
-        double h = 0.0, l = 0.0;
+    for (int64_t ran = 0; (S.parts == 0 || S.done < S.parts) && (max_chunks < 0 || ran < max_chunks); ++ran) {
+        double hl[2] = {0.0, 0.0};
         uint64_t c = 0;
-        rc = bat_reliability_range_ex(n, m, arcs, p, s, t, flags, lo, hi, &h, &l, &c, grad ? t1.data() : nullptr,
-                                      grad ? t0.data() : nullptr);
+        rc = run_part(n, m, arcs, p, s, t, flags, grad, parts_wanted, S, hl, &c, grad ? t1.data() : nullptr,
+                      grad ? t0.data() : nullptr);
         if (rc) return rc;
-        dd_acc(S.R, h, l);
+        dd_acc(S.R, hl[0], hl[1]);
         S.count += c;
         for (int32_t a = 0; grad && a < m; ++a) {
             dd_acc(&S.T1[2 * a], t1[a], 0.0);
@@ -1611,11 +1729,11 @@ int bat_reliability_checkpointed(int32_t n, int32_t m, const bat_arc *arcs, cons
         }
         ++S.done;
         if (path) {
-            rc = checkpoint_write(path, problem, chunks, grad, S);
+            rc = checkpoint_write(path, problem, grad, S);
             if (rc) return rc;
         }
     }
-    if (S.done < chunks) return BAT_PENDING;
+    if (S.parts == 0 || S.done < S.parts) return BAT_PENDING;
     *R_out = S.R[0] + S.R[1];
     *count_out = S.count;
     for (int32_t a = 0; grad && a < m; ++a) {

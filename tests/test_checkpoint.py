@@ -1,12 +1,12 @@
 """Checkpoint files of bat_reliability_checkpointed, checked on the CPU.
 
-The entry point cuts a sweep into the equal divisions of Section 4 (Eq. 6)
-and keeps its running sums in a text file.  A file whose chunks are all
-done returns its result without any device work, and a call with
-max_chunks = 0 only reads the file, so the file format, the resume
-bookkeeping, the problem key and the error paths can be checked here.
-The files are written by these tests from the oracle's own range sums (the
-paper's divisions added as double-doubles), so the stored values are the
+The entry point cuts a sweep into parts and keeps its running sums in a
+text file.  A file whose parts are all done returns its result without any
+device work, and a call with max_chunks = 0 only reads the file.  So the
+file format, the resume bookkeeping, the problem key and the error paths
+can be checked here.  The files are written by these tests with the
+oracle's own sums over a partition of the counter (the equal divisions of
+Section 4, Eq. 6, added as double-doubles), so the stored values are the
 oracle's, not the library's.  The resumed sweeps themselves, bitwise
 against uninterrupted ones, are GPU tests (test_gpu_checkpoint.py).
 """
@@ -39,12 +39,11 @@ def _problem(net, flags, clog, grad):
             f"grad={int(grad)} arcs={_fnv(arcs):016x} p={_fnv(p):016x}")
 
 
-def _oracle_file(net, clog, grad, done=None):
-    """The checkpoint text after `done` chunks (default: all), with the
-    oracle's range sums of each division added in index order."""
+def _oracle_file(net, clog, grad, parts, done=None):
+    """The checkpoint text after `done` of `parts` parts (default: all), with
+    the oracle's sums over the Eq. 6 divisions standing for the parts'."""
     m = net.m
-    c = min(clog, m)
-    chunks = 1 << (m - c)
+    chunks = parts
     done = chunks if done is None else done
     R = (0.0, 0.0)
     cnt = 0
@@ -58,7 +57,8 @@ def _oracle_file(net, clog, grad, done=None):
         if grad:
             T1 = [pbat.dd_add(*T1[i], float(r.T1[i])) for i in range(m)]
             T0 = [pbat.dd_add(*T0[i], float(r.T0[i])) for i in range(m)]
-    lines = ["bat-checkpoint 1", _problem(net, 0, clog, grad), f"chunks {chunks}", f"done {done}",
+    lines = ["bat-checkpoint 1", _problem(net, 0, clog, grad), f"parts {parts}", "launch order=3 items=0 chain=3",
+             f"done {done}",
              f"count {cnt}", f"R {R[0].hex()} {R[1].hex()}"]
     if grad:
         lines.append("T1 " + " ".join(f"{h.hex()} {l.hex()}" for h, l in T1))
@@ -71,8 +71,8 @@ def test_finished_file_returns_its_sums(tmp_path, grad):
     """A file with every division done gives back exactly its sums, and they
     match the whole-sweep oracle (and, for the bridge, the closed form)."""
     B = _B()
-    for net, clog in ((W.bridge(0.9), 2), (W.random_connected(7, 12, seed=5, p_lo=0.3, p_hi=0.97), 9)):
-        text, R, cnt, T1, T0 = _oracle_file(net, clog, grad)
+    for net, clog, parts in ((W.bridge(0.9), 2, 1), (W.random_connected(8, 15, seed=5, p_lo=0.3, p_hi=0.97), 12, 8)):
+        text, R, cnt, T1, T0 = _oracle_file(net, clog, grad, parts)
         f = tmp_path / f"{net.name}.ckpt"
         f.write_text(text)
         out = B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, clog, str(f), grad=grad)
@@ -94,11 +94,11 @@ def test_finished_file_returns_its_sums(tmp_path, grad):
 
 def test_unfinished_file_with_no_chunk_budget_is_pending(tmp_path):
     B = _B()
-    net = W.random_connected(6, 10, seed=3)
-    text = _oracle_file(net, 6, True, done=5)[0]
+    net = W.random_connected(8, 15, seed=3)
+    text = _oracle_file(net, 12, True, 8, done=5)[0]
     f = tmp_path / "c.ckpt"
     f.write_text(text)
-    assert B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, 6, str(f), max_chunks=0,
+    assert B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, 12, str(f), max_chunks=0,
                                           grad=True) is None
     assert f.read_text() == text
     assert not os.path.exists(str(f) + ".tmp")
@@ -106,15 +106,15 @@ def test_unfinished_file_with_no_chunk_budget_is_pending(tmp_path):
 
 def test_file_for_another_problem_is_refused(tmp_path):
     B = _B()
-    net = W.random_connected(6, 10, seed=3)
-    text = _oracle_file(net, 6, False)[0]
+    net = W.random_connected(8, 15, seed=3)
+    text = _oracle_file(net, 12, False, 8)[0]
     f = tmp_path / "c.ckpt"
     f.write_text(text)
     p2 = np.array(net.p)
     p2[4] = np.nextafter(p2[4], 0.0)          # one bit of one probability
-    others = [dict(p=p2), dict(chunk_log2=5), dict(grad=True), dict(directed=True), dict(t=net.t - 1)]
+    others = [dict(p=p2), dict(chunk_log2=11), dict(grad=True), dict(directed=True), dict(t=net.t - 1)]
     for o in others:
-        kw = dict(p=net.p, chunk_log2=6, grad=False, directed=False, t=net.t)
+        kw = dict(p=net.p, chunk_log2=12, grad=False, directed=False, t=net.t)
         kw.update(o)
         with pytest.raises(B.BatError) as e:
             B.bat_reliability_checkpointed(net.n, net.arcs, kw["p"], net.s, kw["t"], kw["chunk_log2"], str(f),
@@ -123,27 +123,36 @@ def test_file_for_another_problem_is_refused(tmp_path):
     assert f.read_text() == text
 
 
-@pytest.mark.parametrize("edit", ["magic", "chunks", "done", "R", "truncate", "trailing"])
+@pytest.mark.parametrize("edit", ["magic", "parts", "too_many_parts", "order", "items", "chain", "done", "R",
+                                  "truncate", "trailing"])
 def test_damaged_files_are_io_errors(tmp_path, edit):
     B = _B()
-    net = W.random_connected(6, 10, seed=3)
-    lines = _oracle_file(net, 6, False)[0].splitlines()
+    net = W.random_connected(8, 15, seed=3)                  # 2^4 iterations of 2048 vectors
+    lines = _oracle_file(net, 12, False, 8)[0].splitlines()
     if edit == "magic":
         lines[0] = "bat-checkpoint 2"
-    elif edit == "chunks":
-        lines[2] = "chunks 17"
+    elif edit == "parts":
+        lines[2] = "parts 6"                  # not a power of two
+    elif edit == "too_many_parts":
+        lines[2] = "parts 32"                 # more parts than work items
+    elif edit == "order":
+        lines[3] = "launch order=4 items=0 chain=3"   # the forward order, without BAT_FORWARD_ORDER
+    elif edit == "items":
+        lines[3] = "launch order=3 items=2 chain=3"   # 4 work items: fewer than 8 parts
+    elif edit == "chain":
+        lines[3] = "launch order=3 items=0 chain=2"
     elif edit == "done":
-        lines[3] = "done 17"
+        lines[4] = "done 9"
     elif edit == "R":
-        lines[5] = "R 0x1p-1"
+        lines[6] = "R 0x1p-1"
     elif edit == "truncate":
-        lines = lines[:4]
+        lines = lines[:5]
     else:
-        lines[4] += " x"
+        lines[5] += " x"
     f = tmp_path / "c.ckpt"
     f.write_text("\n".join(lines) + "\n")
     with pytest.raises(B.BatError) as e:
-        B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, 6, str(f), max_chunks=0)
+        B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, 12, str(f), max_chunks=0)
     assert e.value.code == B.BAT_EIO
 
 

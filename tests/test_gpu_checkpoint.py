@@ -1,7 +1,9 @@
 """Checkpointed sweeps on the GPU: a sweep stopped after some chunks and
 resumed from its file gives bitwise the same R, count and gradient as the
 same chunking run in one call (with or without a file), and both agree
-with the oracle (counts exact, R and T1 / T0 within 1e-12 relative)."""
+with the oracle (counts exact, R and T1 / T0 within 1e-12 relative).
+Each chunk is one part of the whole sweep's work items; the parts must
+cover every vector exactly once, which the exact counts check."""
 import sys
 
 import numpy as np
@@ -47,7 +49,7 @@ def test_resumed_sweep_is_bitwise_the_uninterrupted_one(tmp_path, grad, jit):
             r = B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, clog, f, max_chunks=budget,
                                                grad=grad)
             assert r is None
-            steps.append(open(f).read().splitlines()[3])
+            steps.append(open(f).read().splitlines()[4])
         assert steps == ["done 3", "done 3", "done 8", "done 9"]
         resumed = B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, clog, f, grad=grad)
         assert _same(resumed, whole)
@@ -84,3 +86,50 @@ def test_flags_and_one_chunk(tmp_path):
     one = B.bat_reliability_checkpointed(n, arcs, p, 0, n - 1, 40, None, directed=True)
     rng_all = B.bat_reliability_range(n, arcs, p, 0, n - 1, 0, 1 << m, directed=True)
     assert one[1] == rng_all.count == o.count and abs(one[0] - rng_all.R) <= 1e-15 * rng_all.R
+
+
+@pytest.mark.parametrize("perm", [0, 1, 2, 3])
+def test_chunks_follow_the_whole_sweep_order(tmp_path, perm):
+    """Chunks are divisions of the counter under the arc order a whole
+    sweep would take (here forced by BAT_PERM); the file keeps it, and a
+    resume keeps it even when the whole-sweep order has changed since."""
+    B = _B()
+    net = W.random_connected(11, 20, seed=2002 + perm, p_lo=0.3, p_hi=0.99)
+    old = B.bat_get_option("BAT_PERM")
+    try:
+        B.bat_set_option("BAT_PERM", perm)
+        say("checkpoint order", perm)
+        whole = B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, 16, None, grad=True)
+        f = str(tmp_path / "o.ckpt")
+        assert B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, 16, f, max_chunks=5,
+                                              grad=True) is None
+        launch = open(f).read().splitlines()[3]
+        assert launch.startswith(f"launch order={perm} ")
+        B.bat_set_option("BAT_PERM", (perm + 1) % 4)
+        resumed = B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, 16, f, grad=True)
+        assert open(f).read().splitlines()[3] == launch
+        assert _same(resumed, whole)
+    finally:
+        B.bat_set_option("BAT_PERM", old)
+    o = oracle.reliability(net.n, net.arcs, net.p, net.s, net.t, grad=True)
+    assert whole.count == o.count and abs(whole.R - o.sum) <= 1e-12 * o.sum
+    assert np.allclose(whole.T1, o.T1, rtol=1e-12, atol=0) and np.allclose(whole.T0, o.T0, rtol=1e-12, atol=0)
+
+
+def test_tuned_sweep_in_parts_matches_whole():
+    """The 30-arc random graph (2^30 vectors), tuned: 16 parts against the
+    whole sweep."""
+    B = _B()
+    net = W.config1()
+    say("checkpoint config1")
+    B.bat_autotune(net.n, net.arcs, net.p, net.s, net.t)
+    R, cnt = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+    whole = B.bat_last_launch()
+    got = B.bat_reliability_checkpointed(net.n, net.arcs, net.p, net.s, net.t, 26, None)
+    part = B.bat_last_launch()
+    # the same order and chains; work items no larger, so each part still
+    # fills the GPU; together the parts tile the same counter
+    assert (part.perm, part.chain_log2) == (whole.perm, whole.chain_log2)
+    assert part.chunk_log2 <= whole.chunk_log2
+    assert part.n_chunks * 16 == whole.n_chunks << (whole.chunk_log2 - part.chunk_log2)
+    assert got[1] == cnt and abs(got[0] - R) <= 1e-12 * R
