@@ -40,12 +40,16 @@ PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 1.26e15 bit-ops/s
 #   traffic_bytes: HBM bytes per launch, rocprofv3 FETCH_SIZE x 2.0 +
 #     WRITE_SIZE x 1.0 (KiB), the factors of a plain 1 GiB device copy;
 #   valu_busy: SQ_INSTS_VALU / (256 CUs x GRBM_GUI_ACTIVE cycles);
-#   valu_insts_per_vector: SQ_INSTS_VALU x 64 lanes / 2^40 (lane-ops).
+#   valu_insts_per_vector: SQ_INSTS_VALU x 64 lanes / 2^40 (lane-ops);
+#   salu_busy: SQ_INSTS_SALU / (256 x cycles), the scalar unit's share;
+#   lds_busy: SQ_LDS_IDX_ACTIVE / (256 x cycles).
 MEASURED = {
     "43a630a3f3b13d07/perm3/chunk12/chain3/check1/order1/waves4/super0/window1/simd6/keep1": {
         "traffic_bytes": (54945.3125 * 2.0 + 43996462.40625 * 1.0) * 1024,
         "valu_busy": 0.84,
         "valu_insts_per_vector": 3.58,
+        "salu_busy": 0.31,
+        "lds_busy": 0.06,
     },
 }
 
@@ -307,6 +311,8 @@ def main():
                            "traffic": MEASURED.get(launch_key(li_step), {}).get("traffic_bytes"),
                            "valu_busy": MEASURED.get(launch_key(li_step), {}).get("valu_busy"),
                            "valu_insts_per_vector": MEASURED.get(launch_key(li_step), {}).get("valu_insts_per_vector"),
+                           "salu_busy": MEASURED.get(launch_key(li_step), {}).get("salu_busy"),
+                           "lds_busy": MEASURED.get(launch_key(li_step), {}).get("lds_busy"),
                            "launch": launch_key(li_step),
                            "work_per_vector": insp, "work_unit": "PLSA arc inspections (1 bit-op each)"}
     line = json.dumps(out)
