@@ -304,6 +304,9 @@ def main():
     # one bit-operation each.
     kern_s = float(np.mean(kern_ms)) / 1e3
     insp = cpu["inspections_per_vector"] if cpu else None
+    # the sustained integer VALU rate this device reaches on independent
+    # add / xor chains (library diagnostic), as a second peak
+    lane_peak = B.bat_valu_peak()
     if insp is not None:
         achieved = nvec * insp / kern_s
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_BIT_OPS / 1e12,
@@ -314,6 +317,8 @@ def main():
                            "salu_busy": MEASURED.get(launch_key(li_step), {}).get("salu_busy"),
                            "lds_busy": MEASURED.get(launch_key(li_step), {}).get("lds_busy"),
                            "launch": launch_key(li_step),
+                           "peak_measured": lane_peak * 32 / 1e12,
+                           "frac_measured": achieved / (lane_peak * 32) if lane_peak > 0 else None,
                            "work_per_vector": insp, "work_unit": "PLSA arc inspections (1 bit-op each)"}
     line = json.dumps(out)
     print(line, flush=True)

@@ -377,6 +377,17 @@ typedef struct {
 int bat_last_launch(bat_launch_info *info);
 
 /*
+ * Diagnostic: the sustained integer VALU rate of the current device, in
+ * 32-bit lane operations per second (*lane_ops_per_s), measured with a
+ * kernel of independent add / xor chains (64 blocks of 256 threads per
+ * CU; the best of three timed launches after a warm-up).  Sweeps are
+ * bound by this rate; the nominal figure for 256 CUs at 2.4 GHz is
+ * 256 x 64 x 2.4e9 = 3.93e13.  Blocks the calling thread for a few
+ * milliseconds.  BAT_EINVAL for a NULL pointer, BAT_EDEVICE on a HIP error.
+ */
+int bat_valu_peak(double *lane_ops_per_s);
+
+/*
  * The source text of the graph-specialised kernel that the library hands
  * to hiprtc for this graph (flags: BAT_DIRECTED or 0): the forward sweep,
  * or the gradient sweep when grad != 0, with arc-to-counter-bit order

@@ -34,7 +34,7 @@ EXPORTED = ("bat_version", "bat_last_error", "bat_reliability", "bat_reliability
             "bat_reliability_range", "bat_reliability_batched", "bat_reliability_async",
             "bat_reliability_grad_async", "bat_set_option", "bat_get_option", "bat_autotune",
             "bat_last_launch", "bat_jit_source", "bat_autotune_batched", "bat_reliability_ex",
-            "bat_reliability_range_ex", "bat_reliability_checkpointed")
+            "bat_reliability_range_ex", "bat_reliability_checkpointed", "bat_valu_peak")
 
 
 class bat_arc(ctypes.Structure):
@@ -89,6 +89,7 @@ def _load():
         "bat_reliability_ex": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, P, P, P, P, P], ctypes.c_int),
         "bat_reliability_range_ex": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, u64, u64, P, P, P, P, P],
                                      ctypes.c_int),
+        "bat_valu_peak": ([P], ctypes.c_int),
         "bat_reliability_checkpointed": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, i32, ctypes.c_char_p, i64,
                                           P, P, P, P, P], ctypes.c_int),
     }
@@ -332,6 +333,13 @@ def bat_jit_source(n_nodes: int, arcs, s: int, t: int, grad: bool = False, perm:
     buf = ctypes.create_string_buffer(n.value)
     _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, f, int(grad), perm, buf, ctypes.byref(n)))
     return buf.value.decode()
+
+
+def bat_valu_peak() -> float:
+    """Measured sustained integer VALU rate (32-bit lane-ops/s)."""
+    r = ctypes.c_double(0.0)
+    _check(_lib.bat_valu_peak(ctypes.byref(r)))
+    return r.value
 
 
 def bat_last_launch() -> bat_launch_info:

@@ -1787,6 +1787,43 @@ int bat_reliability_grad_async(int32_t n, int32_t m, const bat_arc *arcs, const 
                         stream);
 }
 
+int bat_valu_peak(double *lane_ops_per_s)
+{
+    t_err.clear();
+    if (!lane_ops_per_s) return fail(BAT_EINVAL, "NULL output pointer");
+    DeviceInfo D;
+    int rc = current_device(D);
+    if (rc) return rc;
+    hipStream_t st;
+    rc = thread_stream(D.id, st);
+    if (rc) return rc;
+    rc = events_ready();
+    if (rc) return rc;
+    void *sink = nullptr;
+    HIPCHK(hipMallocAsync(&sink, 64 * sizeof(u32), st));
+    // 64 blocks of 256 threads per CU; 2048 trips of 16 instructions each
+    const unsigned blocks = (unsigned)std::max(D.cus, 1) * 64u;
+    const u32 iters = 2048;
+    const double ops = (double)blocks * 256.0 * iters * batk::kValuPeakOpsPerTrip;
+    double best = 0.0;
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {  // the first is a warm-up
+        float ms = 0.0f;
+        e = hipEventRecord(t_state.ev[0], st);
+        if (e == hipSuccess) e = batk::valu_peak(st, blocks, iters, (u32 *)sink);
+        if (e == hipSuccess) e = hipEventRecord(t_state.ev[1], st);
+        if (e == hipSuccess) e = hipEventSynchronize(t_state.ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t_state.ev[0], t_state.ev[1]);
+        if (e == hipSuccess && rep > 0 && ms > 0.0f) best = std::max(best, ops / (ms * 1e-3));
+    }
+    const hipError_t ef = hipFreeAsync(sink, st);
+    if (e == hipSuccess) e = ef;
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(BAT_EDEVICE, "bat_valu_peak: %s", hipGetErrorString(e));
+    *lane_ops_per_s = best;
+    return BAT_OK;
+}
+
 int bat_last_launch(bat_launch_info *info)
 {
     if (!info) return fail(BAT_EINVAL, "NULL info");

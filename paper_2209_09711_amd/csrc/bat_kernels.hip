@@ -370,6 +370,32 @@ k_batched_reduce(const batk::BatchEntry *__restrict__ entries, const double *__r
     }
 }
 
+// Sustained integer VALU rate (a diagnostic, no part of the sweep): per loop
+// trip, 8 independent chains of one 32-bit add and one xor, i.e.
+// batk::kValuPeakOpsPerTrip full-rate VALU instructions.  The chains' xor
+// is stored only when it equals a value these inputs practically never
+// give, which keeps every chain live.
+extern "C" __global__ void __launch_bounds__(256) k_valu_peak(u32 iters, u32 *sink)
+{
+    u32 a[8], b[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        a[i] = threadIdx.x * (2u * (u32)i + 1u);
+        b[i] = blockIdx.x + 0x9E3779B9u * (u32)i;
+    }
+    for (u32 k = 0; k < iters; ++k) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            a[i] += b[i];
+            b[i] ^= a[i];
+        }
+    }
+    u32 x = 0u;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x ^= a[i] ^ b[i];
+    if (x == 0x5bd1e995u) sink[threadIdx.x & 63u] = x;
+}
+
 // ------------------------------------------------------------ launchers
 namespace batk {
 
@@ -400,6 +426,12 @@ hipError_t sweep_dyn(hipStream_t st, unsigned blocks, bool grad, int nmax, bool 
 {
     if (directed) sweep_dyn_t<true>(st, blocks, grad, nmax, K);
     else sweep_dyn_t<false>(st, blocks, grad, nmax, K);
+    return hipGetLastError();
+}
+
+hipError_t valu_peak(hipStream_t st, unsigned blocks, u32 iters, u32 *sink)
+{
+    hipLaunchKernelGGL(k_valu_peak, dim3(blocks), dim3(256), 0, st, iters, sink);
     return hipGetLastError();
 }
 

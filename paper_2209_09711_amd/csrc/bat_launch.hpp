@@ -55,6 +55,10 @@ hipError_t build_tables(hipStream_t st, const double *p, const unsigned char *ro
 hipError_t sweep_dyn(hipStream_t st, unsigned blocks, bool grad, int nmax, bool directed, const bat::KParams &K);
 hipError_t reduce(hipStream_t st, const double *part, const bat::u64 *pcount, bat::u64 n_chunks, bat::u32 ncol,
                   double *res, bat::u64 *count);
+// the diagnostic VALU-rate kernel: `blocks` blocks of 256 threads, `iters`
+// loop trips of kValuPeakOpsPerTrip VALU instructions each; sink: 64 u32s
+constexpr int kValuPeakOpsPerTrip = 16;
+hipError_t valu_peak(hipStream_t st, unsigned blocks, bat::u32 iters, bat::u32 *sink);
 hipError_t finalize(hipStream_t st, const double *res, const bat::u64 *count, const int *status,
                     const unsigned char *cb_of_arc, bat::u32 m, bool grad, double *R, bat::u64 *cnt, double *dRdp,
                     double *T1, double *T0, int *status_out);

@@ -86,6 +86,11 @@ def test_null_outputs_rejected():
     assert rc == B.BAT_EINVAL
 
 
+def test_valu_peak_null_output():
+    import paper_2209_09711_amd as B
+    assert B._lib.bat_valu_peak(None) == B.BAT_EINVAL
+
+
 def test_no_oracle_in_product_path():
     """The product package never imports or loads the oracle."""
     pkg = os.path.join(ROOT, "paper_2209_09711_amd")

@@ -891,3 +891,17 @@ def test_launch_info_names_the_kernel():
                     assert li.check_every in (1, 2) and li.item_order in (0, 1)
                     assert ids.setdefault((jit, grad), li.kernel_id) == li.kernel_id
     assert len(set(ids.values())) == 4
+
+
+def test_valu_peak_diagnostic():
+    """The measured integer VALU rate is positive and within a factor of
+    two of one wave64 instruction per CU per clock (256 x 64 x 2.4e9), above
+    or below: the chip's 32-bit vector rate is quoted at 128 lanes per CU per
+    clock for packed FP32, and independent add / xor chains run faster than
+    64 (1.5x measured)."""
+    B = _B()
+    say("valu peak")
+    r = B.bat_valu_peak()
+    nominal = 256 * 64 * 2.4e9
+    say("lane-ops/s", r, r / nominal)
+    assert 0.5 * nominal < r < 2.05 * nominal
