@@ -133,3 +133,28 @@ def test_tuned_sweep_in_parts_matches_whole():
     assert part.chunk_log2 <= whole.chunk_log2
     assert part.n_chunks * 16 == whole.n_chunks << (whole.chunk_log2 - part.chunk_log2)
     assert got[1] == cnt and abs(got[0] - R) <= 1e-12 * R
+
+
+def test_edge_cases(tmp_path):
+    """No arcs; more parts asked for than the sweep has work items (the
+    bridge's 32 vectors are one iteration); s and t in different
+    components; p at 0 and 1."""
+    B = _B()
+    say("checkpoint edge cases")
+    R, cnt = B.bat_reliability_checkpointed(2, np.zeros((0, 2), np.int32), np.zeros(0), 0, 1, 0, None)
+    assert R == 0.0 and cnt == 0
+    b = W.bridge(0.9)
+    f = str(tmp_path / "b.ckpt")
+    R, cnt = B.bat_reliability_checkpointed(b.n, b.arcs, b.p, b.s, b.t, 0, f)
+    assert open(f).read().splitlines()[2] == "parts 1"
+    assert cnt == 16 and abs(R - (2 * .81 + 2 * .729 - 5 * .6561 + 2 * .59049)) <= 1e-15
+    R, cnt = B.bat_reliability_checkpointed(4, [(0, 1), (2, 3)], [0.9, 0.9], 0, 3, 1, None)
+    assert R == 0.0 and cnt == 0
+    net = W.random_connected(10, 16, seed=44)
+    p = np.array(net.p)
+    p[::2] = 1.0
+    p[1::4] = 0.0
+    g = B.bat_reliability_checkpointed(net.n, net.arcs, p, net.s, net.t, 12, None, grad=True)
+    o = oracle.reliability(net.n, net.arcs, p, net.s, net.t, grad=True)
+    assert g.count == o.count and abs(g.R - o.sum) <= 1e-12 * max(o.sum, 1e-300)
+    assert np.all(np.abs(g.dRdp - o.grad) <= 1e-12 * (o.T1 + o.T0) + 1e-300)
