@@ -938,7 +938,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "bat_jit.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
         return fail(BAT_EDEVICE, "hiprtcCreateProgram failed");
-    hiprtcResult rc = hiprtcCompileProgram(prog, 7, o);
+    hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof o / sizeof o[0]), o);
     if (rc != HIPRTC_SUCCESS) {
         size_t ls = 0;
         hiprtcGetProgramLogSize(prog, &ls);
