@@ -253,12 +253,15 @@ def main():
         fw, gr = [], []
         for _ in range(3):
             B.bat_reliability(c4.n, c4.arcs, c4.p, c4.s, c4.t)
-            fw.append(B.bat_last_launch().kernel_ms)
+            li_f = B.bat_last_launch()
+            fw.append(li_f.kernel_ms)
             B.bat_reliability_grad(c4.n, c4.arcs, c4.p, c4.s, c4.t)
-            gr.append(B.bat_last_launch().kernel_ms)
+            li_g = B.bat_last_launch()
+            gr.append(li_g.kernel_ms)
         out["fwd_grad_vs_fwd"] = {"workload": "random n=18 m=36 (seed 220909711/4), R + 36 gradients",
                                   "fwd_kernel_ms": min(fw), "fwd_grad_kernel_ms": min(gr),
-                                  "ratio": min(gr) / min(fw)}
+                                  "ratio": min(gr) / min(fw),
+                                  "fwd_launch": launch_key(li_f), "grad_launch": launch_key(li_g)}
     if not a.no_extras and not a.no_batched:
         # batched: one persistent launch vs the plain forward on every
         # (graph, probability vector) pair of the same workload

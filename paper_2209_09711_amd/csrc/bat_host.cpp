@@ -996,7 +996,7 @@ struct Request {
     // over the whole counter by an odd multiplier (0 = everything)
     u64 sample_items = 0;
     // a part of the counter, or the first part of a split sweep: work items
-    // no larger than the ~64-per-CU size
+    // no larger than fill_item_log2's size
     bool fill = false;
     // one part of a whole sweep split into split_parts (a power of two):
     // part split_index (0 = no split)
@@ -1051,6 +1051,25 @@ struct Launch {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Work-item size (log2 iterations) for `iters` iterations in `parts` launches
+// (0 or 1: one): ~256 work items per CU per launch, so that the last,
+// partly idle round of items is a small share of a launch, but at most 4096
+// and, for one launch where the sweep has that many, at least 32 iterations
+// per item (a split sweep needs the items to deal out into its parts).
+// Measured: the 36-arc graph (2^25 iterations) 6.3 ms at 512 iterations
+// per item against 8.4 ms at 2048 (64 items per CU); the 40-arc grid in 16
+// parts 127 ms against 154 ms (one launch: 118 ms); items of 8 iterations
+// slowed the 30-arc graph's gradient sweep (2.3 against 1.9 ms at 32).
+int fill_item_log2(u64 iters, int cus, u64 parts)
+{
+    const u64 target = iters / ((u64)std::max(cus, 1) * 256ull * std::max<u64>(parts, 1));
+    int c = 0;
+    while (c < 12 && (2ull << c) <= target) ++c;
+    if (parts <= 1)
+        while (c < 5 && (2ull << c) <= iters) ++c;
+    return c;
+}
+
 // Queue tables + sweep + reduce on `stream`.  Allocates the workspace with
 // hipMallocAsync; the caller frees it on the same stream.
 // p_host (synchronous calls) is uploaded with the plan through the thread's
@@ -1079,15 +1098,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     const u64 g_end = g_last | bmask;
     const u64 iters = g_end - g_base + 1;
 
-    // aim at ~64 work items per CU, at most 4096 iterations each; ~256 per
-    // CU in each part of a split sweep, whose launches are short enough for
-    // their last, partly idle round of work items to matter (measured on
-    // the 40-arc grid in 16 parts: 154 ms at 64 per CU, 127 ms at 256, 118
-    // ms unsplit)
-    const u64 per_cu = rq.split_parts ? 256ull * rq.split_parts : 64ull;
-    const u64 target = iters / ((u64)std::max(D.cus, 1) * per_cu);
-    int clog_fill = 0;
-    while (clog_fill < 12 && (2ull << clog_fill) <= target) ++clog_fill;
+    const int clog_fill = fill_item_log2(iters, D.cus, rq.split_parts);
     int clog = tc.chunk_log2;
     // a size tuned for the whole counter would leave a short range's last
     // round of work items mostly idle
@@ -1882,18 +1893,18 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
     const u64 total = 1ull << m;
     const u32 ubits = m > bat::kWordBits ? (u32)m - bat::kWordBits : 0u;
     // the automatic work-item size (as queue_sweep picks it)
-    int clog_auto = 0;
-    {
-        u64 target = (1ull << ubits) / ((u64)std::max(D.cus, 1) * 64ull);
-        while (clog_auto < 12 && (2ull << clog_auto) <= target) ++clog_auto;
-    }
+    const int clog_auto = fill_item_log2(1ull << ubits, D.cus, 1);
     struct Cand {
         int clog, check, jit, perm, chain, waves = -1, super_restart = -1, simd_waves = -1, keep_bottom = -1;
     };
     constexpr double kTuneMargin = 0.01;
     auto measure = [&](const Cand &c, double &ns, bool grad = false) -> bool {
         ns = 1e300;
-        for (int rep = 0; rep < 3; ++rep) {  // the first pass warms the JIT cache
+        // the first pass warms the JIT cache; then the best of at least two
+        // timed passes, more for short samples (up to ~40 ms of timed
+        // kernel, at most 6 passes), whose times scatter more
+        double timed_ms = 0.0;
+        for (int rep = 0; rep < 7 && (rep < 3 || timed_ms < 40.0); ++rep) {
             Request tmpl{};
             tmpl.force_chunk_log2 = c.clog;
             tmpl.force_check = c.check;
@@ -1911,7 +1922,10 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
             u64 cnt = 0;
             bat_launch_info li;
             if (run_sync(n, m, arcs, p, s, t, 0, total, grad, res, cnt, &tmpl) || bat_last_launch(&li)) return false;
-            if (rep > 0) ns = std::min(ns, li.kernel_ms * 1e6 / (double)li.vectors);
+            if (rep > 0) {
+                ns = std::min(ns, li.kernel_ms * 1e6 / (double)li.vectors);
+                timed_ms += li.kernel_ms;
+            }
         }
         return true;
     };
