@@ -159,6 +159,22 @@ def plsa(n, arcs, s, t, x, directed=False):
     return bool(rc), int(L.value), lay
 
 
+def plsa_work(n, arcs, s, t, x, directed=False):
+    """PLSA on G(X) with its work counters: (connected, layers, arc
+    inspections).  These counters are what the range sums' ``layers`` and
+    ``inspections`` add up over the vectors of a range."""
+    a = _arcs(arcs)
+    xa = np.ascontiguousarray(np.asarray(x, dtype=np.uint8))
+    assert xa.shape[0] == a.shape[0]
+    L = ctypes.c_int32(0)
+    I = ctypes.c_int64(0)
+    rc = _load().orc_plsa(n, a.shape[0], _ptr(a), _ptr(xa), s, t, int(directed),
+                          ctypes.byref(L), ctypes.byref(I), None)
+    if rc < 0:
+        raise OracleError(rc)
+    return bool(rc), int(L.value), int(I.value)
+
+
 def pr(p, x) -> float:
     pv = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
     xa = np.ascontiguousarray(np.asarray(x, dtype=np.uint8))

@@ -95,3 +95,39 @@ def factoring(n, arcs, p, s, t):
         return pe * r_con + (1 - pe) * r_del
 
     return rec([(int(a), int(b)) for a, b in arcs], P, s, t)
+
+
+def layered_search_work(n, arcs, s, t, x, directed=False):
+    """The layered search of Section 3.2 written out on node sets, with its
+    work: (connected, layers built, arc inspections).
+
+    Layer 1 is {s}.  Expanding a layer looks at every arc end at each of its
+    nodes (working or not: the state is what the look reads), and the next
+    layer is the set of nodes not in any earlier layer reached over a
+    working arc.  The search stops when a layer comes out empty (layers =
+    the non-empty ones) or holds t (layers = t's layer index).  A self-loop
+    is one arc end at its node; an undirected arc is an end at each of its
+    two nodes, a directed one only at its tail.
+    """
+    ends = {v: [] for v in range(n)}
+    for i, (a, b) in enumerate(arcs):
+        a, b = int(a), int(b)
+        ends[a].append((i, b))
+        if not directed and a != b:
+            ends[b].append((i, a))
+    placed = {s}
+    layer = {s}
+    built = 1
+    looks = 0
+    while True:
+        found = set()
+        for u in layer:
+            looks += len(ends[u])
+            found.update(v for i, v in ends[u] if x[i] and v not in placed)
+        if not found:
+            return False, built, looks
+        placed |= found
+        built += 1
+        if t in found:
+            return True, built, looks
+        layer = found

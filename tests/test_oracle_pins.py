@@ -18,7 +18,7 @@ import pytest
 import bat_workloads as W
 import oracle
 from oracle import frontier_dp, pbat
-from exact_ref import brute, factoring
+from exact_ref import brute, factoring, layered_search_work
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 EPS = 2.0 ** -53
@@ -129,6 +129,94 @@ def test_plsa_stops_on_empty_layer():
     # s isolated: L_2 is empty at once (STEP P2)
     conn, nl, lay = oracle.plsa(3, [(1, 2)], 0, 2, [1])
     assert not conn and nl == 1
+
+
+# The layered search's work counters (layers built, arc inspections) are the
+# algorithmic work the benchmark's roofline divides by, so they are pinned
+# like any other output: values worked out by hand on small cases, and an
+# independently written set-based search (tests/exact_ref.py) over whole
+# ranges.  An inspection is one look at one arc end of a node being expanded,
+# whatever the arc's state: counting only working arcs, or counting the
+# expansion of the layer that holds t, fails the hand values below.
+
+@pytest.mark.parametrize("case", [
+    # Figure 1, every arc working (Table 3): expand {1}: 2 ends; expand
+    # {2, 3}: 4 + 2 ends; t = 4 joins layer 3.
+    ("figure1", None, (1, 1, 1, 1, 1, 1), False, (True, 3, 8)),
+    # bridge 0-1, 0-2, 1-2, 1-3, 2-3, s = 0, t = 3, all working: 2 + (3 + 3)
+    ("bridge", None, (1, 1, 1, 1, 1), False, (True, 3, 8)),
+    # only 0-1 works: {0} 2 ends -> {1}; {1} 3 ends -> nothing new
+    ("bridge", None, (1, 0, 0, 0, 0), False, (False, 2, 5)),
+    # nothing works: {0} 2 ends, layer 2 empty
+    ("bridge", None, (0, 0, 0, 0, 0), False, (False, 1, 2)),
+    # 0-2 and 2-3 work: {0} 2 ends -> {2}; {2} 3 ends -> {3} = t
+    ("bridge", None, (0, 1, 0, 0, 1), False, (True, 3, 5)),
+    # directed bridge, all working: out-ends only, 2 + (2 + 1)
+    ("bridge", None, (1, 1, 1, 1, 1), True, (True, 3, 5)),
+    # a self-loop at s is one end: {0} 2 ends -> {1}; {1} 2 ends -> {2}
+    ("custom", (3, [(0, 0), (0, 1), (1, 2)], 0, 2), (1, 1, 1), False, (True, 3, 4)),
+    # parallel arcs are separate ends, a failed copy still inspected: {0}
+    # 2 ends -> {1}; {1} 3 ends (both copies and 1-2, which is down)
+    ("custom", (3, [(0, 1), (0, 1), (1, 2)], 0, 2), (0, 1, 0), False, (False, 2, 5)),
+])
+def test_plsa_work_hand_values(case):
+    kind, g, x, directed, want = case
+    if kind == "figure1":
+        f = W.figure1()
+        n, arcs, s, t = f.n, f.arcs, f.s, f.t
+    elif kind == "bridge":
+        b = W.bridge()
+        n, arcs, s, t = b.n, b.arcs, b.s, b.t
+    else:
+        n, arcs, s, t = g
+    assert oracle.plsa_work(n, arcs, s, t, x, directed=directed) == want
+    assert layered_search_work(n, arcs, s, t, x, directed=directed) == want
+
+
+def _range_work(n, arcs, s, t, m, lo, hi, directed=False):
+    lay = insp = 0
+    for c in range(lo, hi):
+        x = [(c >> (m - 1 - i)) & 1 for i in range(m)]   # arc i at bit m-1-i (Eq. 3)
+        _, l, k = layered_search_work(n, arcs, s, t, x, directed=directed)
+        lay += l
+        insp += k
+    return lay, insp
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_range_work_counters_against_independent_search(seed):
+    """Whole-range layer and inspection totals equal the set-based search's."""
+    rng = random.Random(seed)
+    directed = seed % 3 == 2
+    if seed % 2:
+        net = W.random_multigraph(rng.randint(3, 7), rng.randint(1, 10), seed=seed, p_lo=0.1, p_hi=0.9)
+    else:
+        n = rng.randint(4, 8)
+        net = W.random_connected(n, rng.randint(n - 1, min(11, n * (n - 1) // 2)), seed=seed)
+    m = net.m
+    r = oracle.reliability_range(net.n, net.arcs, net.p, net.s, net.t, 0, 1 << m, directed=directed)
+    assert (r.layers, r.inspections) == _range_work(net.n, net.arcs, net.s, net.t, m, 0, 1 << m, directed)
+
+
+def test_range_work_counters_grid_sample():
+    """The 5x5 grid's counters (the headline's work per vector) on spread
+    slices of Eq. 6 divisions, the way the benchmark samples them."""
+    net = W.config2()
+    m, chi = net.m, 1 << 17
+    for i in pbat.spread_divisions(chi, 4):
+        lo, _ = pbat.division_bounds(m, chi, i)
+        r = oracle.reliability_range(net.n, net.arcs, net.p, net.s, net.t, lo, lo + 300)
+        assert (r.layers, r.inspections) == _range_work(net.n, net.arcs, net.s, net.t, m, lo, lo + 300)
+    # the harness adds the divisions' counters in full
+    divs = pbat.spread_divisions(1 << 30, 3)
+    pr = pbat.run(net.n, net.arcs, net.p, net.s, net.t, 1 << 30, divisions=divs, processes=1)
+    want = [0, 0]
+    for i in divs:
+        lo, hi = pbat.division_bounds(m, 1 << 30, i)
+        w = _range_work(net.n, net.arcs, net.s, net.t, m, lo, hi)
+        want[0] += w[0]
+        want[1] += w[1]
+    assert (pr.layers, pr.inspections) == tuple(want)
 
 
 # ---------------------------------------------------------- Section 5.2 / 5.3
