@@ -23,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bat_oracle.c")
+_SRC_MS = os.path.join(_HERE, "ms_oracle.c")
 _LIB = os.path.join(_HERE, "libbat_oracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -34,10 +35,11 @@ ORC_ETOOBIG = -2
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, single thread)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in (_SRC, _SRC_MS))
+    if force or stale:
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+                               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, _SRC_MS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -70,6 +72,16 @@ def _load():
             lib.orc_dec_inv_fwd.restype = None
             lib.orc_bat_next_fwd.argtypes = [i32, P]
             lib.orc_bat_next_fwd.restype = ctypes.c_int
+            lib.orc_ms_validate.argtypes = [i32, i32, P, P, P, P, i32, i32, i32]
+            lib.orc_ms_validate.restype = ctypes.c_int
+            lib.orc_ms_decode.argtypes = [i32, P, u64, P]
+            lib.orc_ms_decode.restype = None
+            lib.orc_ms_next.argtypes = [i32, P, P]
+            lib.orc_ms_next.restype = ctypes.c_int
+            lib.orc_ms_range.argtypes = [i32, i32, P, P, P, P, i32, i32, i32, i32, u64, u64, P, P, P, P]
+            lib.orc_ms_range.restype = ctypes.c_int
+            lib.orc_ms_maxflow.argtypes = [i32, i32, P, P, i32, i32, i32]
+            lib.orc_ms_maxflow.restype = i64
             _lib = lib
     return _lib
 
@@ -217,3 +229,86 @@ def net_reliability(net, p=None, grad=False, directed=False) -> RangeResult:
     """Convenience wrapper taking a ``bat_workloads.Network``."""
     return reliability(net.n, net.arc_array(), net.p if p is None else p, net.s, net.t,
                        grad=grad, directed=directed)
+
+
+# ------------------------------------------------------------ multi-state
+# Arcs with sigma_i states, state k of arc i having capacity cap_i(k) and
+# probability w_i(k); a vector meets demand d when the maximum s-t flow is at
+# least d (ms_oracle.c states the reading).  States are passed per arc, arc
+# 0's states first: a list of per-arc sequences or one flat array.
+
+@dataclass
+class MsResult:
+    sum: float
+    sum_hi: float
+    sum_lo: float
+    count: int
+    U: float
+    inspections: int
+
+
+def _flat(per_arc, dtype):
+    if per_arc is None:
+        return None
+    if isinstance(per_arc, np.ndarray) and per_arc.ndim == 1:
+        return np.ascontiguousarray(per_arc.astype(dtype))
+    return np.ascontiguousarray(np.concatenate([np.asarray(v, dtype=dtype).reshape(-1) for v in per_arc])
+                                if len(per_arc) else np.zeros(0, dtype=dtype))
+
+
+def ms_validate(n, arcs, sigma, cap, w, s, t, d) -> int:
+    a = _arcs(arcs)
+    sg = np.ascontiguousarray(np.asarray(sigma, dtype=np.int32))
+    return _load().orc_ms_validate(n, a.shape[0], _ptr(a), _ptr(sg), _ptr(_flat(cap, np.int32)),
+                                   _ptr(_flat(w, np.float64)), s, t, d)
+
+
+def ms_decode(sigma, c: int) -> tuple:
+    sg = np.ascontiguousarray(np.asarray(sigma, dtype=np.int32))
+    x = np.zeros(max(len(sg), 1), dtype=np.int32)
+    _load().orc_ms_decode(len(sg), _ptr(sg), c, _ptr(x))
+    return tuple(int(v) for v in x[:len(sg)])
+
+
+def ms_sequence(sigma):
+    """Every vector in the order the generalised BAT update visits them."""
+    lib = _load()
+    sg = np.ascontiguousarray(np.asarray(sigma, dtype=np.int32))
+    x = np.zeros(max(len(sg), 1), dtype=np.int32)
+    out = [tuple(int(v) for v in x[:len(sg)])]
+    while lib.orc_ms_next(len(sg), _ptr(sg), _ptr(x)):
+        out.append(tuple(int(v) for v in x[:len(sg)]))
+    return out
+
+
+def ms_maxflow(n, arcs, capx, s, t, directed=False) -> int:
+    a = _arcs(arcs)
+    c = np.ascontiguousarray(np.asarray(capx, dtype=np.int64))
+    return int(_load().orc_ms_maxflow(n, a.shape[0], _ptr(a), _ptr(c), s, t, int(directed)))
+
+
+def ms_reliability_range(n, arcs, sigma, cap, w, s, t, d, c_lo, c_hi, directed=False) -> MsResult:
+    a = _arcs(arcs)
+    m = a.shape[0]
+    sg = np.ascontiguousarray(np.asarray(sigma, dtype=np.int32))
+    if sg.shape[0] != m:
+        raise OracleError(ORC_EINVAL)
+    cf = _flat(cap, np.int32)
+    wf = _flat(w, np.float64)
+    sum2 = np.zeros(2)
+    usum2 = np.zeros(2)
+    cnt = ctypes.c_uint64(0)
+    stats = np.zeros(1, dtype=np.int64)
+    rc = _load().orc_ms_range(n, m, _ptr(a), _ptr(sg), _ptr(cf), _ptr(wf), s, t, d, int(directed), int(c_lo),
+                              int(c_hi), _ptr(sum2), ctypes.byref(cnt), _ptr(usum2), _ptr(stats))
+    if rc != ORC_OK:
+        raise OracleError(rc)
+    return MsResult(float(sum2[0] + sum2[1]), float(sum2[0]), float(sum2[1]), int(cnt.value),
+                    float(usum2[0] + usum2[1]), int(stats[0]))
+
+
+def ms_reliability(n, arcs, sigma, cap, w, s, t, d, directed=False) -> MsResult:
+    N = 1
+    for v in sigma:
+        N *= int(v)
+    return ms_reliability_range(n, arcs, sigma, cap, w, s, t, d, 0, N, directed=directed)
