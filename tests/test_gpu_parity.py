@@ -583,16 +583,30 @@ def test_item_orders(order):
 
 
 def test_autotune_choice_keeps_results():
+    """After tuning, the tuned forward and gradient launches still match
+    the frontier DP (an independent exact method), not just the untuned
+    launch."""
     B = _B()
     net = W.random_connected(16, 34, seed=8, p_lo=0.6, p_hi=0.99)
+    Rd, cd = frontier_dp.reliability(net.n, net.arcs, net.p, net.s, net.t)
     R0, c0 = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+    assert c0 == cd and rel_ok(R0, Rd)
     ns = B.bat_autotune(net.n, net.arcs, net.p, net.s, net.t)
     say("autotune ns/vector", ns)
     assert 0.0 < ns < 1.0
     R1, c1 = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
-    assert c1 == c0 and rel_ok(R1, R0)
+    assert c1 == cd and rel_ok(R1, Rd)
     g = B.bat_reliability_grad(net.n, net.arcs, net.p, net.s, net.t)
-    assert g.count == c0 and rel_ok(g.R, R0)
+    assert g.count == cd and rel_ok(g.R, Rd)
+    # the tuned gradient launch against per-arc DP runs: T1_i = R|p_i<-1,
+    # T0_i = R|p_i<-0, on a spread of arcs
+    for i in range(0, net.m, 5):
+        q = net.p.copy()
+        q[i] = 1.0
+        t1 = frontier_dp.reliability(net.n, net.arcs, q, net.s, net.t)[0]
+        q[i] = 0.0
+        t0 = frontier_dp.reliability(net.n, net.arcs, q, net.s, net.t)[0]
+        assert rel_ok(g.T1[i], t1) and rel_ok(g.T0[i], t0), (i, g.T1[i], t1, g.T0[i], t0)
 
 
 def test_jit_disk_cache(tmp_path, monkeypatch):
@@ -784,9 +798,15 @@ def test_batched_vs_plain_and_oracle(n_pvec):
         for j in sorted({0, n_pvec // 2, n_pvec - 1}):
             Rp, cp = B.bat_reliability(n, arcs, pblocks[g][j], s, t)
             assert cnt[g] == cp and rel_ok(R[g, j], Rp), (g, j, R[g, j], Rp)
+        # every probability vector index against the oracle (or the frontier
+        # DP), spread over the graphs
+        j = g % n_pvec
         if len(arcs) <= 16:
-            o = oracle.reliability(n, arcs, pblocks[g][0], s, t)
-            assert cnt[g] == o.count and rel_ok(R[g, 0], o.sum)
+            o = oracle.reliability(n, arcs, pblocks[g][j], s, t)
+            assert cnt[g] == o.count and rel_ok(R[g, j], o.sum), (g, j)
+        else:
+            Rd, cd = frontier_dp.reliability(n, arcs, pblocks[g][j], s, t)
+            assert cnt[g] == cd and rel_ok(R[g, j], Rd), (g, j)
 
 
 @pytest.mark.parametrize("k", [0, 3, 4, 5, 6])
@@ -809,6 +829,8 @@ def test_batched_chain_lengths(k):
 
 
 def test_batched_autotune_keeps_results():
+    """The tuned batched launch against the frontier DP on every graph, each
+    with another probability vector."""
     B = _B()
     graphs, pblocks = _batch_inputs(777, 12, 9)
     R0, c0 = B.bat_reliability_batched(graphs, pblocks)
@@ -817,6 +839,10 @@ def test_batched_autotune_keeps_results():
     assert 0.0 < ms < 1e4
     R1, c1 = B.bat_reliability_batched(graphs, pblocks)
     assert np.array_equal(c1, c0) and np.allclose(R1, R0, rtol=1e-12, atol=0)
+    for g, (n, arcs, s_, t_) in enumerate(graphs):
+        j = g % 9
+        Rd, cd = frontier_dp.reliability(n, arcs, pblocks[g][j], s_, t_)
+        assert c1[g] == cd and rel_ok(R1[g, j], Rd), (g, j, R1[g, j], Rd)
 
 
 def test_batched_config3_workload():
@@ -825,12 +851,22 @@ def test_batched_config3_workload():
     nets, pvs = W.config3()
     graphs = [(n.n, n.arcs, n.s, n.t) for n in nets]
     say("config3 batched", len(graphs))
+    # the launch the benchmark times: tuned on this batch
+    B.bat_autotune_batched(graphs, pvs)
     R, cnt = B.bat_reliability_batched(graphs, pvs)
     R2, cnt2 = B.bat_reliability_batched(graphs, pvs)
     assert np.array_equal(R, R2) and np.array_equal(cnt, cnt2)       # deterministic
     for g, net in enumerate(nets):
-        Rd, cd = frontier_dp.reliability(net.n, net.arcs, pvs[g][0], net.s, net.t)
-        assert cnt[g] == cd and rel_ok(R[g, 0], Rd), (g, R[g, 0], Rd)
+        # p-vector 0 and p-vector g mod 32 of every graph: every index 0..31
+        # is checked against the frontier DP (an independent exact method)
+        for j in sorted({0, g % 32}):
+            Rd, cd = frontier_dp.reliability(net.n, net.arcs, pvs[g][j], net.s, net.t)
+            assert cnt[g] == cd and rel_ok(R[g, j], Rd), (g, j, R[g, j], Rd)
+    big = max(range(len(nets)), key=lambda i: (nets[i].m, nets[i].n))
+    for j in range(32):
+        net = nets[big]
+        Rd, cd = frontier_dp.reliability(net.n, net.arcs, pvs[big][j], net.s, net.t)
+        assert cnt[big] == cd and rel_ok(R[big, j], Rd), (big, j, R[big, j], Rd)
     for g in range(0, len(nets), 17):
         net = nets[g]
         for j in (5, 31):
