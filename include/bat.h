@@ -251,6 +251,34 @@ int bat_reliability_grad_async(int32_t n_nodes, int32_t n_arcs, const bat_arc *a
                                double *T0_dev, int32_t *status_dev, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward sweep of bat_reliability_async with the same arguments, the same
+ * device-side check of p and results within rounding of it (1e-12
+ * relative; the count is exact), run without any allocation.
+ *
+ * Its device workspace is a fixed array of BAT_NOALLOC_SCRATCH_BYTES bytes
+ * inside the library, one per GPU, held from the first call on that GPU
+ * until the process ends.  The call makes no hipMalloc, hipFree or other
+ * device allocation: it runs the ahead-of-time kernels only (never a
+ * run-time compiled one, whose module would take device memory), and work
+ * items grow until their partial sums fit the array.  A problem whose sums
+ * do not fit even then (about 2^53 or more state vectors) returns
+ * BAT_ETOOBIG before anything is queued.  Every call's kernels write the
+ * parts of the array they read, so no state carries over between calls.
+ *
+ * All calls on one GPU share its array: calls whose work overlaps on that
+ * GPU (other threads, other streams, or queued work of an earlier call
+ * still running on another stream) race and give wrong results.  Order
+ * them, e.g. by using one stream.
+ */
+#define BAT_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+int bat_reliability_noalloc(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs,
+                            const double *p_dev, int32_t s, int32_t t, double *R_dev,
+                            uint64_t *count_dev, int32_t *status_dev, void *stream);
+
+/*
  * Tuning and diagnostics.
  *
  * bat_set_option / bat_get_option read and set process-wide knobs (also

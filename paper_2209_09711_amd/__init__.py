@@ -34,7 +34,8 @@ EXPORTED = ("bat_version", "bat_last_error", "bat_reliability", "bat_reliability
             "bat_reliability_range", "bat_reliability_batched", "bat_reliability_async",
             "bat_reliability_grad_async", "bat_set_option", "bat_get_option", "bat_autotune",
             "bat_last_launch", "bat_jit_source", "bat_autotune_batched", "bat_reliability_ex",
-            "bat_reliability_range_ex", "bat_reliability_checkpointed", "bat_valu_peak")
+            "bat_reliability_range_ex", "bat_reliability_checkpointed", "bat_valu_peak",
+            "bat_reliability_noalloc")
 
 
 class bat_arc(ctypes.Structure):
@@ -80,6 +81,7 @@ def _load():
         "bat_reliability_batched": ([i32, P, P, P, P, P, i32, P, P, P], ctypes.c_int),
         "bat_reliability_async": ([i32, i32, P, P, i32, i32, P, P, P, P], ctypes.c_int),
         "bat_reliability_grad_async": ([i32, i32, P, P, i32, i32, P, P, P, P, P, P, P], ctypes.c_int),
+        "bat_reliability_noalloc": ([i32, i32, P, P, i32, i32, P, P, P, P], ctypes.c_int),
         "bat_set_option": ([ctypes.c_char_p, i64], ctypes.c_int),
         "bat_get_option": ([ctypes.c_char_p, P], ctypes.c_int),
         "bat_autotune": ([i32, i32, P, P, i32, i32, P], ctypes.c_int),
@@ -353,6 +355,13 @@ def bat_reliability_async(n_nodes: int, arcs, p_dev_ptr: int, s: int, t: int, R_
     a = _arcs(arcs)
     _check(_lib.bat_reliability_async(n_nodes, a.shape[0], _ptr(a), p_dev_ptr, s, t, R_dev_ptr, count_dev_ptr,
                                       status_dev_ptr, stream))
+
+
+def bat_reliability_noalloc(n_nodes: int, arcs, p_dev_ptr: int, s: int, t: int, R_dev_ptr: int,
+                            count_dev_ptr: int, status_dev_ptr: Optional[int], stream: int):
+    a = _arcs(arcs)
+    _check(_lib.bat_reliability_noalloc(n_nodes, a.shape[0], _ptr(a), p_dev_ptr, s, t, R_dev_ptr, count_dev_ptr,
+                                        status_dev_ptr, stream))
 
 
 def bat_reliability_grad_async(n_nodes: int, arcs, p_dev_ptr: int, s: int, t: int, R_dev_ptr: int,

@@ -640,6 +640,31 @@ int events_ready()
     return BAT_OK;
 }
 
+// ------------------------------------------------- fixed device scratch
+// The workspace of bat_reliability_noalloc: a fixed array in device memory,
+// one copy per GPU the library runs on, held until the process ends.  In
+// host code `scratch` names the symbol, not a device address: the address
+// of a GPU's copy comes from hipGetSymbolAddress with that GPU current, once
+// per device, and only that address is passed to kernels and copies.
+constexpr size_t kNoAllocScratchBytes = BAT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+int noalloc_scratch(int dev, char *&ptr)
+{
+    static std::mutex mu;
+    static std::map<int, char *> addr;  // device -> its copy of `scratch`
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *a = nullptr;
+        HIPCHK(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+        if (!a) return fail(BAT_EDEVICE, "no device address for the fixed scratch on device %d", dev);
+        it = addr.emplace(dev, (char *)a).first;
+    }
+    ptr = it->second;
+    return BAT_OK;
+}
+
 // ------------------------------------------------------------ JIT cache
 struct JitEntry {
     hipModule_t mod = nullptr;
@@ -1075,8 +1100,16 @@ int fill_item_log2(u64 iters, int cus, u64 parts)
 // p_host (synchronous calls) is uploaded with the plan through the thread's
 // pinned staging buffer into its reused workspace; otherwise rq.p_dev is
 // already on the device and the workspace is allocated on the stream.
+// fixed_ws (fixed_cap bytes): a caller-provided device workspace instead of
+// an allocation.  The ahead-of-time kernels then run (loading a compiled
+// kernel module would take device memory), and work items grow until the
+// partials fit; BAT_ETOOBIG when even items of 2^kFixedMaxItemLog2
+// iterations do not fit.  Every byte the sweep reads is written first by
+// this call's own kernels and copy, so the workspace needs no clearing.
+constexpr int kFixedMaxItemLog2 = 24;
+
 int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const TuneChoice &tc, hipStream_t stream,
-                Launch &L, const double *p_host = nullptr)
+                Launch &L, const double *p_host = nullptr, char *fixed_ws = nullptr, size_t fixed_cap = 0)
 {
     const u32 m = (u32)rq.m;
     const u32 ubits = m > (u32)bat::kWordBits ? m - bat::kWordBits : 0u;
@@ -1087,6 +1120,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     bool use_jit = false;
     if (tc.jit == 1) use_jit = true;
     else if (tc.jit == 2) use_jit = (rq.c_hi - rq.c_lo) >= (1ull << 32) || (P.N > 32 && (rq.c_hi - rq.c_lo) >= (1ull << 22));
+    if (fixed_ws) use_jit = false;
     // warm-started chains need >= k iteration bits; k = 3..6 (the gradient
     // sweep keeps at most 4 fast bits: k <= 4)
     u32 ck = tc.chain < 0 ? 3u : (tc.chain >= 6 ? 6u : (tc.chain >= 3 ? (u32)tc.chain : 0u));
@@ -1109,6 +1143,34 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     if (rq.grad) f = std::min<u32>(f, bat::kGradFastMax);
     if (chain) f = std::max<u32>(f, ck);
     if (f > ubits) f = ubits;
+    const u32 ncol = rq.grad ? 1u + 2u * m : 1u;
+    // workspace: input block (p | row, cb_of_arc maps | relaxation program),
+    // then tables | partials | counts | output block (res | count | status)
+    auto in_size = [&]() {
+        size_t o = 0;
+        if (p_host) o = align_up(o + sizeof(double) * (m + 1), 256);
+        o = align_up(o + 128, 256);
+        return align_up(o + sizeof(u32) * (P.prog.size() + 1), 256);
+    };
+    auto ws_size = [&](u64 n_chunks) {
+        size_t o = in_size();
+        o = align_up(o + sizeof(double) * bat::kTables, 256);
+        o = align_up(o + sizeof(double) * 2 * ncol * n_chunks, 256);
+        o = align_up(o + sizeof(u64) * n_chunks, 256);
+        return align_up(o + sizeof(double) * 2 * ncol + sizeof(u64) + 64, 256);
+    };
+    if (fixed_ws) {
+        if (rq.split_parts || rq.sample_items) return fail(BAT_EINVAL, "a fixed workspace sweeps whole ranges only");
+        while (ws_size((iters + (1ull << clog) - 1) >> clog) > fixed_cap) {
+            if (clog >= kFixedMaxItemLog2)
+                return fail(BAT_ETOOBIG,
+                            "%llu iterations need %zu bytes of fixed scratch even in work items of 2^%d "
+                            "iterations; it holds %zu",
+                            (unsigned long long)iters, ws_size((iters + (1ull << clog) - 1) >> clog), clog,
+                            fixed_cap);
+            ++clog;
+        }
+    }
 
     bat::KParams K;
     memset(&K, 0, sizeof K);
@@ -1153,7 +1215,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     K.seg_log = f;
     K.check_every = tc.check_every >= 2 ? 2u : 1u;
     K.chain = chain ? ck : 0u;
-    K.ncol = rq.grad ? 1u + 2u * m : 1u;
+    K.ncol = ncol;
     K.window_test = (chain && O.window_test.load() != 0) ? 1u : 0u;
     K.n_nodes = (u32)P.N;
     K.s = (u32)P.S;
@@ -1163,8 +1225,6 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     chain_codes(P, K.ck_code);
     L.ncol = K.ncol;
 
-    // workspace: input block (p | row, cb_of_arc maps | relaxation program),
-    // then tables | partials | counts | output block (res | count | status)
     size_t off = 0;
     const size_t o_p = off;
     if (p_host) off = align_up(off + sizeof(double) * (m + 1), 256);
@@ -1187,7 +1247,13 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     char *ws = nullptr;
     Scratch *S = nullptr;
     const size_t out_host_off = align_up(in_bytes, 256);
-    if (p_host) {
+    if (in_bytes != in_size() || off != ws_size(K.n_chunks))
+        return fail(BAT_EDEVICE, "workspace layout mismatch (%zu/%zu, %zu/%zu)", in_bytes, in_size(), off,
+                    ws_size(K.n_chunks));
+    if (fixed_ws) {
+        if (off > fixed_cap) return fail(BAT_ETOOBIG, "needs %zu bytes of fixed scratch; it holds %zu", off, fixed_cap);
+        ws = fixed_ws;
+    } else if (p_host) {
         int rc = scratch_reserve(D.id, stream, off, out_host_off + out_bytes, S);
         if (rc) return rc;
         ws = S->dev;
@@ -1796,6 +1862,32 @@ int bat_reliability_grad_async(int32_t n, int32_t m, const bat_arc *arcs, const 
 {
     return async_common(n, m, arcs, p_dev, s, t, R_dev, count_dev, true, dRdp_dev, T1_dev, T0_dev, status_dev,
                         stream);
+}
+
+int bat_reliability_noalloc(int32_t n, int32_t m, const bat_arc *arcs, const double *p_dev, int32_t s, int32_t t,
+                            double *R_dev, uint64_t *count_dev, int32_t *status_dev, void *stream)
+{
+    t_err.clear();
+    if (!R_dev || !count_dev) return fail(BAT_EINVAL, "NULL output pointer");
+    if (m > 0 && !p_dev) return fail(BAT_EINVAL, "p_dev is NULL");
+    Prepared X;
+    TuneChoice tc;
+    int rc = prepare(n, m, arcs, nullptr, s, t, false, true, nullptr, X, tc);
+    if (rc) return rc;
+    // set-up on this device's first call: the address of its scratch copy
+    char *ws = nullptr;
+    rc = noalloc_scratch(X.D.id, ws);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Request rq{};
+    rq.n = n; rq.m = m; rq.s = s; rq.t = t; rq.arcs = arcs; rq.p_dev = p_dev;
+    rq.c_lo = 0; rq.c_hi = 1ull << m; rq.grad = false;
+    Launch L;
+    rc = queue_sweep(rq, X.P, X.D, tc, st, L, nullptr, ws, kNoAllocScratchBytes);
+    if (rc) return rc;
+    HIPCHK(batk::finalize(st, (const double *)L.res, (const u64 *)L.count, (const int *)L.status, L.cb_of_arc,
+                          (u32)m, false, R_dev, (u64 *)count_dev, nullptr, nullptr, nullptr, (int *)status_dev));
+    return BAT_OK;
 }
 
 int bat_valu_peak(double *lane_ops_per_s)
