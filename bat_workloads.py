@@ -206,3 +206,87 @@ def figure1(reversed_table1: bool = True) -> Network:
     table1 = [0.99, 0.89, 0.88, 0.95, 0.85, 0.87]
     p = table1[::-1] if reversed_table1 else table1
     return Network("figure1", 5, arcs, 0, 3, np.asarray(p, dtype=np.float64))
+
+
+# ------------------------------------------------------------ multi-state
+# Arcs with several states (the solution space of prod_i sigma_i vectors):
+# state k of arc i carries capacity cap[i][k] with probability w[i][k]; the
+# question is whether the maximum s-t flow reaches a demand d.  The paper
+# has no multi-state benchmark, so these stand in: three capacity levels
+# 0, 1, 2 per arc (failed, degraded, full), mostly at full capacity.
+
+@dataclass
+class MsNetwork:
+    name: str
+    n: int
+    arcs: List[Tuple[int, int]]
+    s: int
+    t: int
+    sigma: List[int]
+    cap: List[List[int]]
+    w: List[np.ndarray]
+    d: int
+
+    @property
+    def m(self) -> int:
+        return len(self.arcs)
+
+    @property
+    def space(self) -> int:
+        N = 1
+        for k in self.sigma:
+            N *= int(k)
+        return N
+
+    def cap_flat(self) -> np.ndarray:
+        return np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.int32) for c in self.cap])
+                                    if self.cap else np.zeros(0, dtype=np.int32))
+
+    def w_flat(self) -> np.ndarray:
+        return np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in self.w])
+                                    if self.w else np.zeros(0, dtype=np.float64))
+
+
+def three_level_weights(rng: np.random.Generator, m: int) -> List[np.ndarray]:
+    """Per arc: failed w ~ U[0.02, 0.10], degraded w ~ U[0.10, 0.30], the
+    rest at full capacity."""
+    out = []
+    for _ in range(m):
+        w0 = rng.uniform(0.02, 0.10)
+        w1 = rng.uniform(0.10, 0.30)
+        out.append(np.array([w0, w1, 1.0 - w0 - w1]))
+    return out
+
+
+def ms_bridge(d: int = 2) -> MsNetwork:
+    """The bridge with three capacity levels per arc, w = (0.05, 0.15, 0.80)."""
+    b = bridge()
+    return MsNetwork(f"ms_bridge_d{d}", b.n, list(b.arcs), b.s, b.t, [3] * 5, [[0, 1, 2]] * 5,
+                     [np.array([0.05, 0.15, 0.80])] * 5, d)
+
+
+def ms_random(n: int, m: int, seed, d: int = 2, s: int = 0, t: int | None = None) -> MsNetwork:
+    """Random connected graph (the recipe above) with three capacity levels."""
+    rng = seed if isinstance(seed, np.random.Generator) else np.random.default_rng(seed)
+    arcs = random_connected_arcs(n, m, rng)
+    w = three_level_weights(rng, m)
+    return MsNetwork(f"ms_rand_n{n}_m{m}_d{d}", n, arcs, s, n - 1 if t is None else t, [3] * m,
+                     [[0, 1, 2]] * m, w, d)
+
+
+def ms_mixed(n: int, m: int, seed) -> MsNetwork:
+    """Arbitrary multigraph (self-loops, parallel arcs), 1 to 4 states per
+    arc with random capacities 0..3 and random weights, demand 1 to 3."""
+    rng = np.random.default_rng(seed)
+    arcs = [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(m)]
+    s, t = (int(x) for x in rng.choice(n, size=2, replace=False))
+    sigma = [int(rng.integers(1, 5)) for _ in range(m)]
+    cap = [[int(c) for c in rng.integers(0, 4, size=k)] for k in sigma]
+    w = [rng.dirichlet(np.ones(k)) for k in sigma]
+    return MsNetwork(f"ms_mixed_n{n}_m{m}", n, arcs, s, t, sigma, cap, w, int(rng.integers(1, 4)))
+
+
+def config_ms() -> MsNetwork:
+    """Multi-state workload: random connected graph, 10 nodes, m = 18,
+    three capacity levels per arc, demand 2; 3^18 state vectors."""
+    return ms_random(10, 18, rng_for(5), d=2)

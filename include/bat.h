@@ -279,6 +279,48 @@ int bat_reliability_noalloc(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs
                             uint64_t *count_dev, int32_t *status_dev, void *stream);
 
 /*
+ * Multi-state arcs.  The paper sizes the solution space of arcs with
+ * sigma_i states as prod_i sigma_i (Section 4.1) and names multi-state
+ * network reliability as the next problem (Section 6) without defining it;
+ * these entry points take the multi-state flow network reading:
+ *
+ *   arc i is in state k (0 <= k < n_states[i]) with probability w_i(k) and
+ *   then carries at most capacity_i(k) units of flow, in either direction
+ *   (from u to v only with BAT_DIRECTED); a state vector X meets demand d
+ *   when the maximum s-t flow is at least d;
+ *   R_d = sum over X meeting d of prod_i w_i(x_i), count = their number.
+ *
+ * With two states of capacity 0 and 1 (w = 1 - p, p) and d = 1 this is the
+ * binary problem of Eq. 1.  The vectors are enumerated by the BAT
+ * generalised to mixed radix: index c (0-based) is the vector whose
+ * coordinates, arc 0 most significant, are the digits of c in the bases
+ * n_states[i]; the next vector raises the last coordinate below its top
+ * state and returns every later one to state 0 (Rule 1 for sigma_i = 2).
+ *
+ * Arguments: n_states[n_arcs]; capacity and w hold sum(n_states) entries,
+ * arc 0's states first (capacity NULL: state k has capacity k).  Limits:
+ * n_nodes <= 32, n_arcs <= 32, 1 <= n_states[i] <= 32, sum(n_states) <=
+ * 1024, capacities in [0, 2^20], 1 <= demand <= 1024, prod n_states <=
+ * 2^62 (else BAT_ETOOBIG or BAT_EINVAL).  Each w_i(k) must lie in [0, 1];
+ * they are used as given (the library does not check that an arc's sum is
+ * 1).  flags: 0 or BAT_DIRECTED.  Host pointers; synchronous, on the
+ * calling thread's stream; the same workspace rules as bat_reliability.
+ *
+ * bat_ms_reliability sweeps every vector (in any arc order it likes: R and
+ * the count are sums).  bat_ms_reliability_range sweeps indices
+ * [c_lo, c_hi) in the order above and returns the partial sum as a
+ * double-double (R_hi + R_lo) and its count.
+ */
+int bat_ms_reliability(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const int32_t *n_states,
+                       const int32_t *capacity, const double *w, int32_t s, int32_t t, int32_t demand,
+                       uint32_t flags, double *R_out, uint64_t *count_out);
+
+int bat_ms_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs,
+                             const int32_t *n_states, const int32_t *capacity, const double *w,
+                             int32_t s, int32_t t, int32_t demand, uint32_t flags, uint64_t c_lo,
+                             uint64_t c_hi, double *R_hi, double *R_lo, uint64_t *count_out);
+
+/*
  * Tuning and diagnostics.
  *
  * bat_set_option / bat_get_option read and set process-wide knobs (also

@@ -138,3 +138,44 @@ def spread_divisions(chi: int, k: int) -> List[int]:
             seen.add(i)
             out.append(i)
     return sorted(out)
+
+
+def run_ranges(jobs, processes: Optional[int] = None):
+    """Oracle calls on (n, arcs, p, s, t, lo, hi) index ranges of several
+    networks in one process pool; per job: (R, count, inspections, layers),
+    plus the pool's wall time (for timing samples that span many graphs)."""
+    work = [(n, np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1, 2)),
+             np.ascontiguousarray(np.asarray(p, dtype=np.float64)), s, t, lo, hi, False, False)
+            for (n, a, p, s, t, lo, hi) in jobs]
+    procs = processes or os.cpu_count() or 1
+    t0 = time.perf_counter()
+    if procs == 1 or len(work) == 1:
+        outs = [_work(j) for j in work]
+    else:
+        ctx = mp.get_context("fork")
+        with ctx.Pool(min(procs, len(work))) as pool:
+            outs = pool.map(_work, work, chunksize=1)
+    wall = time.perf_counter() - t0
+    return [(sh + sl, c, ins, ly) for (sh, sl, c, _t1, _t0, ins, ly) in outs], wall
+
+
+def _ms_work(args):
+    from . import ms_reliability_range
+    n, arcs, sigma, cap, w, s, t, d, lo, hi = args
+    r = ms_reliability_range(n, arcs, sigma, cap, w, s, t, d, lo, hi)
+    return r.sum_hi + r.sum_lo, r.count, r.inspections
+
+
+def run_ms_ranges(net, ranges, processes: Optional[int] = None):
+    """The multi-state oracle on index ranges of one network, in one process
+    pool: per range (R, count, inspections), plus the wall time."""
+    jobs = [(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d, lo, hi) for lo, hi in ranges]
+    procs = processes or os.cpu_count() or 1
+    t0 = time.perf_counter()
+    if procs == 1 or len(jobs) == 1:
+        outs = [_ms_work(j) for j in jobs]
+    else:
+        ctx = mp.get_context("fork")
+        with ctx.Pool(min(procs, len(jobs))) as pool:
+            outs = pool.map(_ms_work, jobs, chunksize=1)
+    return outs, time.perf_counter() - t0

@@ -35,7 +35,7 @@ EXPORTED = ("bat_version", "bat_last_error", "bat_reliability", "bat_reliability
             "bat_reliability_grad_async", "bat_set_option", "bat_get_option", "bat_autotune",
             "bat_last_launch", "bat_jit_source", "bat_autotune_batched", "bat_reliability_ex",
             "bat_reliability_range_ex", "bat_reliability_checkpointed", "bat_valu_peak",
-            "bat_reliability_noalloc")
+            "bat_reliability_noalloc", "bat_ms_reliability", "bat_ms_reliability_range")
 
 
 class bat_arc(ctypes.Structure):
@@ -82,6 +82,9 @@ def _load():
         "bat_reliability_async": ([i32, i32, P, P, i32, i32, P, P, P, P], ctypes.c_int),
         "bat_reliability_grad_async": ([i32, i32, P, P, i32, i32, P, P, P, P, P, P, P], ctypes.c_int),
         "bat_reliability_noalloc": ([i32, i32, P, P, i32, i32, P, P, P, P], ctypes.c_int),
+        "bat_ms_reliability": ([i32, i32, P, P, P, P, i32, i32, i32, ctypes.c_uint32, P, P], ctypes.c_int),
+        "bat_ms_reliability_range": ([i32, i32, P, P, P, P, i32, i32, i32, ctypes.c_uint32, u64, u64, P, P, P],
+                                     ctypes.c_int),
         "bat_set_option": ([ctypes.c_char_p, i64], ctypes.c_int),
         "bat_get_option": ([ctypes.c_char_p, P], ctypes.c_int),
         "bat_autotune": ([i32, i32, P, P, i32, i32, P], ctypes.c_int),
@@ -217,6 +220,57 @@ def bat_reliability_range(n_nodes: int, arcs, p, s: int, t: int, c_lo: int, c_hi
         _check(_lib.bat_reliability_range(n_nodes, m, _ptr(a), _ptr(pv), s, t, int(c_lo), int(c_hi),
                                           ctypes.byref(hi), ctypes.byref(lo), ctypes.byref(cnt), _ptr(T1), _ptr(T0)))
     return RangeResult(hi.value, lo.value, cnt.value, None if T1 is None else T1[:m], None if T0 is None else T0[:m])
+
+
+def _ms_args(arcs, n_states, capacity, w):
+    a = _arcs(arcs)
+    m = a.shape[0]
+    sg = np.ascontiguousarray(np.asarray(n_states, dtype=np.int32).reshape(-1))
+    if sg.shape[0] != m:
+        raise BatError(BAT_EINVAL, f"n_states has {sg.shape[0]} entries for {m} arcs")
+    total = int(sg.sum()) if m else 0
+
+    def flat(x, dt):
+        if x is None:
+            return None
+        if isinstance(x, np.ndarray) and x.ndim == 1:
+            v = np.ascontiguousarray(x, dtype=dt)
+        else:
+            v = np.ascontiguousarray(np.concatenate([np.asarray(r, dtype=dt).reshape(-1) for r in x])
+                                     if len(x) else np.zeros(0, dtype=dt))
+        if v.shape[0] != total:
+            raise BatError(BAT_EINVAL, f"{v.shape[0]} per-state entries for {total} states")
+        return v
+
+    return a, m, sg, flat(capacity, np.int32), flat(w, np.float64)
+
+
+def bat_ms_reliability(n_nodes: int, arcs, n_states, capacity, w, s: int, t: int, demand: int,
+                       directed: bool = False) -> Tuple[float, int]:
+    """Multi-state arcs: R_d and the count of state vectors whose maximum
+    s-t flow reaches `demand`.  capacity and w: per arc, its states'
+    capacities (None: state k carries k) and probabilities, as a list of
+    sequences or one flat array."""
+    a, m, sg, cf, wf = _ms_args(arcs, n_states, capacity, w)
+    R = ctypes.c_double(0.0)
+    cnt = ctypes.c_uint64(0)
+    _check(_lib.bat_ms_reliability(n_nodes, m, _ptr(a), _ptr(sg), _ptr(cf), _ptr(wf), s, t, demand,
+                                   _flags(directed), ctypes.byref(R), ctypes.byref(cnt)))
+    return R.value, cnt.value
+
+
+def bat_ms_reliability_range(n_nodes: int, arcs, n_states, capacity, w, s: int, t: int, demand: int,
+                             c_lo: int, c_hi: int, directed: bool = False) -> RangeResult:
+    """Partial sums over mixed-radix indices [c_lo, c_hi) (arc 0 most
+    significant)."""
+    a, m, sg, cf, wf = _ms_args(arcs, n_states, capacity, w)
+    hi = ctypes.c_double(0.0)
+    lo = ctypes.c_double(0.0)
+    cnt = ctypes.c_uint64(0)
+    _check(_lib.bat_ms_reliability_range(n_nodes, m, _ptr(a), _ptr(sg), _ptr(cf), _ptr(wf), s, t, demand,
+                                         _flags(directed), int(c_lo), int(c_hi), ctypes.byref(hi),
+                                         ctypes.byref(lo), ctypes.byref(cnt)))
+    return RangeResult(hi.value, lo.value, cnt.value, None, None)
 
 
 def bat_reliability_ex(n_nodes: int, arcs, p, s: int, t: int, directed: bool = False, grad: bool = False):

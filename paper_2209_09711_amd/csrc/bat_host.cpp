@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cerrno>
 #include <chrono>
@@ -1677,6 +1678,178 @@ int run_part(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int32_t
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------ multi-state
+// Arcs with sigma_i states (bat_ms.hip): validate, order the arcs for the
+// flow searches, and sweep [c_lo, c_hi) of the mixed-radix counter.
+int ms_validate(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, const int32_t *cap, const double *w,
+                int32_t s, int32_t t, int32_t d, uint32_t flags, u64 &N, int32_t &n_table)
+{
+    if (flags & ~(uint32_t)BAT_DIRECTED) return fail(BAT_EINVAL, "unknown flags 0x%x", flags);
+    if (n < 2 || m < 0) return fail(BAT_EINVAL, "need n_nodes >= 2 and n_arcs >= 0 (got %d, %d)", n, m);
+    if (n > batk::kMsMaxNodes || m > batk::kMsMaxArcs)
+        return fail(BAT_ETOOBIG, "multi-state arcs: at most %d nodes and %d arcs (got %d, %d)", batk::kMsMaxNodes,
+                    batk::kMsMaxArcs, n, m);
+    if (s < 0 || s >= n || t < 0 || t >= n || s == t) return fail(BAT_EINVAL, "bad terminals s=%d t=%d", s, t);
+    if (d < 1 || d > batk::kMsMaxDemand) return fail(BAT_EINVAL, "demand %d outside [1, %d]", d, batk::kMsMaxDemand);
+    if (m > 0 && (!arcs || !sigma || !w)) return fail(BAT_EINVAL, "NULL arcs, n_states or probabilities");
+    N = 1;
+    n_table = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        if (arcs[i].u < 0 || arcs[i].u >= n || arcs[i].v < 0 || arcs[i].v >= n)
+            return fail(BAT_EINVAL, "arc %d has a node outside [0, %d)", i, n);
+        if (sigma[i] < 1 || sigma[i] > batk::kMsMaxStates)
+            return fail(BAT_EINVAL, "arc %d has %d states, outside [1, %d]", i, sigma[i], batk::kMsMaxStates);
+        for (int32_t k = 0; k < sigma[i]; ++k) {
+            const double x = w[n_table + k];
+            if (!(x >= 0.0 && x <= 1.0)) return fail(BAT_EINVAL, "probability of arc %d state %d is %g", i, k, x);
+            if (cap && (cap[n_table + k] < 0 || cap[n_table + k] > batk::kMsMaxCapacity))
+                return fail(BAT_EINVAL, "capacity of arc %d state %d outside [0, %d]", i, k, batk::kMsMaxCapacity);
+        }
+        n_table += sigma[i];
+        if (n_table > batk::kMsMaxTable)
+            return fail(BAT_ETOOBIG, "more than %d (arc, state) pairs", batk::kMsMaxTable);
+        if ((u64)sigma[i] > (1ull << 62) / N) return fail(BAT_ETOOBIG, "more than 2^62 state vectors");
+        N *= (u64)sigma[i];
+    }
+    return BAT_OK;
+}
+
+int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, const int32_t *cap, const double *w,
+           int32_t s, int32_t t, int32_t d, uint32_t flags, bool whole, u64 c_lo, u64 c_hi, double &R_hi,
+           double &R_lo, u64 &count)
+{
+    u64 N = 0;
+    int32_t n_table = 0;
+    int rc = ms_validate(n, m, arcs, sigma, cap, w, s, t, d, flags, N, n_table);
+    if (rc) return rc;
+    if (whole) {
+        c_lo = 0;
+        c_hi = N;
+    }
+    if (c_lo > c_hi || c_hi > N)
+        return fail(BAT_EINVAL, "range [%llu, %llu) outside [0, %llu)", (unsigned long long)c_lo,
+                    (unsigned long long)c_hi, (unsigned long long)N);
+    // Sweep order.  A whole space may take any arc order (R and the count
+    // are sums over every vector): arcs near s first, by breadth-first
+    // distance of their nearer end, so one search sweep reaches far.  A
+    // range keeps the caller's order, in which its indices are read.
+    std::vector<int> ord(m);
+    for (int i = 0; i < m; ++i) ord[i] = i;
+    if (whole && m > 1) {
+        std::vector<int> dist(n, 1 << 30);
+        std::vector<int> q{s};
+        dist[s] = 0;
+        for (size_t h = 0; h < q.size(); ++h)
+            for (int i = 0; i < m; ++i) {
+                const int a = arcs[i].u, b = arcs[i].v, x = q[h];
+                const int y = a == x ? b : (b == x ? a : -1);
+                if (y >= 0 && dist[y] > dist[x] + 1) {
+                    dist[y] = dist[x] + 1;
+                    q.push_back(y);
+                }
+            }
+        auto key = [&](int i) {
+            const int a = dist[arcs[i].u], b = dist[arcs[i].v];
+            return std::make_pair(std::min(a, b), std::max(a, b));
+        };
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key(x) < key(y); });
+    }
+    batk::MsParams K;
+    memset(&K, 0, sizeof K);
+    K.m = (u32)m;
+    K.n = (u32)n;
+    K.s = (u32)s;
+    K.t = (u32)t;
+    K.d = (u32)d;
+    K.directed = (flags & BAT_DIRECTED) ? 1u : 0u;
+    K.n_table = (u32)n_table;
+    std::vector<int> first(m + 1, 0);
+    for (int i = 0; i < m; ++i) first[i + 1] = first[i] + sigma[i];
+    std::vector<int32_t> capt(n_table);
+    std::vector<double> wt(n_table);
+    u32 o = 0;
+    for (int j = 0; j < m; ++j) {
+        const int i = ord[j];
+        K.sig[j] = (u32)sigma[i];
+        K.off[j] = o;
+        K.u[j] = (unsigned char)arcs[i].u;
+        K.v[j] = (unsigned char)arcs[i].v;
+        for (int k = 0; k < sigma[i]; ++k) {
+            capt[o + k] = cap ? cap[first[i] + k] : k;
+            wt[o + k] = w[first[i] + k];
+        }
+        o += (u32)sigma[i];
+    }
+    // launch shape: ~32K wavefront work items, each 64 runs of `run` indices
+    const u64 span = c_hi - c_lo;
+    const u64 target = 32768;
+    K.run = std::max<u64>(1, (span + 64 * target - 1) / (64 * target));
+    K.n_items = span ? (span + 64 * K.run - 1) / (64 * K.run) : 0;
+    K.c_lo = c_lo;
+    K.c_hi = c_hi;
+    DeviceInfo D;
+    rc = current_device(D);
+    if (rc) return rc;
+    hipStream_t st;
+    rc = thread_stream(D.id, st);
+    if (rc) return rc;
+    // workspace: input (cap | w tables) | partials | counts | output (res | count)
+    const size_t o_cap = 0;
+    const size_t o_w = align_up(o_cap + sizeof(int32_t) * (n_table + 1), 256);
+    const size_t in_bytes = align_up(o_w + sizeof(double) * (n_table + 1), 256);
+    const u64 items = std::max<u64>(K.n_items, 1);
+    const size_t o_part = in_bytes;
+    const size_t o_pc = align_up(o_part + sizeof(double) * 2 * items, 256);
+    const size_t o_res = align_up(o_pc + sizeof(u64) * items, 256);
+    const size_t o_cnt = o_res + 2 * sizeof(double);
+    const size_t out_bytes = o_cnt + sizeof(u64) - o_res;
+    const size_t total = align_up(o_cnt + sizeof(u64) + 64, 256);
+    Scratch *S = nullptr;
+    const size_t out_host_off = in_bytes;
+    rc = scratch_reserve(D.id, st, total, out_host_off + out_bytes, S);
+    if (rc) return rc;
+    char *ws = S->dev;
+    memcpy(S->host + o_cap, capt.data(), sizeof(int32_t) * n_table);
+    memcpy(S->host + o_w, wt.data(), sizeof(double) * n_table);
+    HIPCHK(hipMemcpyAsync(ws, S->host, in_bytes, hipMemcpyHostToDevice, st));
+    K.cap = (const int *)(ws + o_cap);
+    K.w = (const double *)(ws + o_w);
+    K.part = (double *)(ws + o_part);
+    K.pcount = (u64 *)(ws + o_pc);
+    double *res = (double *)(ws + o_res);
+    u64 *cnt = (u64 *)(ws + o_cnt);
+    rc = events_ready();
+    if (rc) return rc;
+    const u64 blocks = (K.n_items + bat::kWavesPerBlock - 1) / bat::kWavesPerBlock;
+    if (blocks > 0x7fffffffull) return fail(BAT_ETOOBIG, "too many work items (%llu)", (unsigned long long)blocks);
+    HIPCHK(hipEventRecord(t_state.ev[0], st));
+    HIPCHK(hipEventRecord(t_state.ev[1], st));
+    if (blocks) HIPCHK(batk::ms_sweep(st, (unsigned)blocks, K));
+    HIPCHK(hipEventRecord(t_state.ev[2], st));
+    HIPCHK(batk::reduce(st, (const double *)K.part, (const u64 *)K.pcount, K.n_items, 1, res, cnt));
+    HIPCHK(hipEventRecord(t_state.ev[3], st));
+    char *out = S->host + out_host_off;
+    HIPCHK(hipMemcpyAsync(out, ws + o_res, out_bytes, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bat_launch_info &I = t_state.info;
+    memset(&I, 0, sizeof I);
+    I.vectors = span;
+    I.n_chunks = (int32_t)std::min<u64>(K.n_items, 0x7fffffff);
+    I.chunk_log2 = -1;
+    I.relaxations = m;
+    I.kernel_id = aot_kernel_id("k_ms_flow", m <= 16 ? 16 : 32, K.directed != 0);
+    I.block_waves = bat::kWavesPerBlock;
+    t_state.have_launch = true;
+    memcpy(&R_hi, out, sizeof(double));
+    memcpy(&R_lo, out + sizeof(double), sizeof(double));
+    memcpy(&count, out + 2 * sizeof(double), sizeof(u64));
+    return BAT_OK;
+}
+
+}  // namespace
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -1887,6 +2060,38 @@ int bat_reliability_noalloc(int32_t n, int32_t m, const bat_arc *arcs, const dou
     if (rc) return rc;
     HIPCHK(batk::finalize(st, (const double *)L.res, (const u64 *)L.count, (const int *)L.status, L.cb_of_arc,
                           (u32)m, false, R_dev, (u64 *)count_dev, nullptr, nullptr, nullptr, (int *)status_dev));
+    return BAT_OK;
+}
+
+int bat_ms_reliability(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *n_states, const int32_t *capacity,
+                       const double *w, int32_t s, int32_t t, int32_t demand, uint32_t flags, double *R_out,
+                       uint64_t *count_out)
+{
+    t_err.clear();
+    if (!R_out || !count_out) return fail(BAT_EINVAL, "NULL output pointer");
+    double hi = 0.0, lo = 0.0;
+    u64 c = 0;
+    int rc = ms_run(n, m, arcs, n_states, capacity, w, s, t, demand, flags, true, 0, 0, hi, lo, c);
+    if (rc) return rc;
+    *R_out = hi + lo;
+    *count_out = c;
+    return BAT_OK;
+}
+
+int bat_ms_reliability_range(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *n_states,
+                             const int32_t *capacity, const double *w, int32_t s, int32_t t, int32_t demand,
+                             uint32_t flags, uint64_t c_lo, uint64_t c_hi, double *R_hi, double *R_lo,
+                             uint64_t *count_out)
+{
+    t_err.clear();
+    if (!R_hi || !R_lo || !count_out) return fail(BAT_EINVAL, "NULL output pointer");
+    double hi = 0.0, lo = 0.0;
+    u64 c = 0;
+    int rc = ms_run(n, m, arcs, n_states, capacity, w, s, t, demand, flags, false, c_lo, c_hi, hi, lo, c);
+    if (rc) return rc;
+    *R_hi = hi;
+    *R_lo = lo;
+    *count_out = c;
     return BAT_OK;
 }
 

@@ -50,6 +50,30 @@ hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, const BatchP
 hipError_t batched_reduce(hipStream_t st, const BatchEntry *entries, unsigned n_entries, const double *part,
                           const bat::u64 *pcount, bat::u32 n_pvec, double *R, bat::u64 *counts);
 
+// ---- multi-state arcs (bat_ms.hip)
+constexpr int kMsMaxArcs = 32;     // arc masks and reach sets are 32-bit words
+constexpr int kMsMaxNodes = 32;
+constexpr int kMsMaxStates = 32;   // per arc
+constexpr int kMsMaxTable = 1024;  // sum of the arcs' state counts (LDS tables)
+constexpr int kMsMaxDemand = 1024;
+constexpr int kMsMaxCapacity = 1 << 20;
+
+struct MsParams {
+    bat::u64 c_lo, c_hi;   // index range of the mixed-radix counter (arc 0 most significant)
+    bat::u64 run;          // consecutive indices per lane in a work item
+    bat::u64 n_items;      // wavefront work items: item i covers [c_lo + 64 i run, c_lo + 64 (i+1) run)
+    bat::u32 m, n, s, t, d, directed;
+    bat::u32 n_table;      // sum of the state counts
+    bat::u32 sig[kMsMaxArcs];  // states of arc i
+    bat::u32 off[kMsMaxArcs];  // first table entry of arc i
+    unsigned char u[kMsMaxArcs], v[kMsMaxArcs];
+    const int *cap;        // [n_table] capacity of (arc, state), arc 0's states first
+    const double *w;       // [n_table] probability of (arc, state)
+    double *part;          // [n_items][2] double-double partials
+    bat::u64 *pcount;      // [n_items]
+};
+hipError_t ms_sweep(hipStream_t st, unsigned blocks, const MsParams &P);
+
 hipError_t build_tables(hipStream_t st, const double *p, const unsigned char *row, bat::u32 m, bat::u32 f,
                         double *T, int *status);
 hipError_t sweep_dyn(hipStream_t st, unsigned blocks, bool grad, int nmax, bool directed, const bat::KParams &K);

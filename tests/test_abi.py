@@ -201,3 +201,45 @@ def test_header_is_plain_c(tmp_path):
                         "-I", os.path.join(ROOT, "include"), "-c", str(f), "-o", str(tmp_path / "abi.o")],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(demand=0), -1),                                    # demand below 1
+    (dict(demand=1025), -1),                                 # demand above the limit
+    (dict(n_states=[2, 0]), -1),                             # an arc with no state
+    (dict(n_states=[2, 33]), -1),                            # too many states for one arc
+    (dict(capacity=[[0, 1], [0, -1]]), -1),                  # negative capacity
+    (dict(w=[[0.5, 0.5], [1.5, -0.5]]), -1),                 # probability outside [0, 1]
+    (dict(w=[[0.5, 0.5], [float("nan"), 0.5]]), -1),         # NaN
+    (dict(s=1, t=1), -1),                                    # s == t
+    (dict(n=33), -2),                                        # more nodes than the flow test's masks
+])
+def test_multistate_validation_without_device(kw, code):
+    import paper_2209_09711_amd as B
+    args = dict(n=3, arcs=[(0, 1), (1, 2)], n_states=[2, 2], capacity=[[0, 1], [0, 1]], w=[[0.5, 0.5], [0.5, 0.5]],
+                s=0, t=2, demand=1)
+    args.update(kw)
+    if "n_states" in kw and "capacity" not in kw:
+        args["capacity"] = None
+        args["w"] = [[0.5] * max(k, 0) for k in kw["n_states"]]
+    with pytest.raises(B.BatError) as e:
+        B.bat_ms_reliability(args["n"], args["arcs"], args["n_states"], args["capacity"], args["w"], args["s"],
+                             args["t"], args["demand"])
+    assert e.value.code == code
+    assert B.bat_last_error() != ""
+
+
+def test_multistate_size_limits_without_device():
+    import paper_2209_09711_amd as B
+    with pytest.raises(B.BatError) as e:                     # 33 arcs
+        B.bat_ms_reliability(3, [(0, 1)] * 33, [1] * 33, None, [[1.0]] * 33, 0, 2, 1)
+    assert e.value.code == B.BAT_ETOOBIG
+    with pytest.raises(B.BatError) as e:                     # 32^13 > 2^62 vectors
+        B.bat_ms_reliability(3, [(0, 1)] * 13, [32] * 13, None, [[1 / 32] * 32] * 13, 0, 2, 1)
+    assert e.value.code == B.BAT_ETOOBIG
+    with pytest.raises(B.BatError) as e:                     # a range past the end of the space
+        B.bat_ms_reliability_range(3, [(0, 1), (1, 2)], [2, 3], None, [[0.5, 0.5], [0.2, 0.3, 0.5]], 0, 2, 1, 0, 7)
+    assert e.value.code == B.BAT_EINVAL
+    with pytest.raises(B.BatError) as e:                     # unknown flag bits via a bad n_states length
+        B.bat_ms_reliability(3, [(0, 1), (1, 2)], [2], None, [[0.5, 0.5]], 0, 2, 1)
+    assert e.value.code == B.BAT_EINVAL

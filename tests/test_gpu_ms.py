@@ -1,0 +1,152 @@
+"""GPU parity for multi-state arcs: the HIP flow sweep against the oracle.
+
+Bars: counts bit-exact; R within 1e-12 relative (absolute when R = 0).
+Parity here is against the multi-state oracle, which the paper does not
+pin (it defines only the binary problem); the oracle is pinned by the binary
+reduction, scipy's max flow with exact rationals and closed forms
+(tests/test_ms_oracle.py).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import bat_workloads as W
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+def _B():
+    import paper_2209_09711_amd as B
+    return B
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _ok(got, want):
+    return got == want == 0.0 or abs(got - want) <= REL * abs(want)
+
+
+def _both(net, directed=False):
+    B = _B()
+    R, c = B.bat_ms_reliability(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d, directed=directed)
+    o = oracle.ms_reliability(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d, directed=directed)
+    return R, c, o
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("directed", [False, True])
+def test_bridge_three_levels(d, directed):
+    net = W.ms_bridge(d)
+    say("ms bridge", d, directed)
+    R, c, o = _both(net, directed)
+    assert c == o.count and _ok(R, o.sum), (R, o.sum, c, o.count)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_binary_states_match_binary_path(seed):
+    """Two states of capacity 0 and 1 with d = 1 are the binary problem:
+    the multi-state sweep equals the binary HIP path and the binary oracle."""
+    B = _B()
+    net = W.random_connected(9, 15, seed=seed, p_lo=0.1, p_hi=0.95) if seed % 2 else \
+        W.random_multigraph(7, 13, seed=seed, p_lo=0.1, p_hi=0.95)
+    m = net.m
+    w = [[1.0 - float(p), float(p)] for p in net.p]
+    say("ms binary", net.name)
+    R, c = B.bat_ms_reliability(net.n, net.arcs, [2] * m, [[0, 1]] * m, w, net.s, net.t, 1)
+    Rb, cb = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+    o = oracle.reliability(net.n, net.arcs, net.p, net.s, net.t)
+    assert c == cb == o.count
+    assert _ok(R, o.sum) and _ok(Rb, o.sum)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_mixed_states_against_oracle(seed):
+    """Multigraphs with self-loops and parallel arcs, 1-4 states per arc,
+    capacities 0-3, demands 1-3, both directions of arc reading."""
+    rng = np.random.default_rng(seed)
+    net = W.ms_mixed(int(rng.integers(2, 9)), int(rng.integers(0, 12)), seed=seed)
+    directed = seed % 3 == 2
+    say("ms mixed", seed, net.name, net.space, net.d, directed)
+    R, c, o = _both(net, directed)
+    assert c == o.count and _ok(R, o.sum), (seed, R, o.sum, c, o.count)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_random_three_levels(d):
+    net = W.ms_random(8, 13, seed=100 + d, d=d)
+    say("ms random", net.name, net.space)
+    R, c, o = _both(net)
+    assert c == o.count and _ok(R, o.sum)
+
+
+def test_ranges_against_oracle():
+    """Index ranges in the mixed-radix order of the caller's arcs: ragged
+    lengths, a single vector, the last vector, an empty range."""
+    B = _B()
+    net = W.ms_random(9, 14, seed=7, d=2)
+    N = net.space
+    cases = [(0, N), (0, 1), (N - 1, N), (12345, 12345), (777, 777 + 64 * 37 + 5), (N // 3, N // 3 + 100003)]
+    for lo, hi in cases:
+        say("ms range", lo, hi)
+        r = B.bat_ms_reliability_range(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d, lo, hi)
+        o = oracle.ms_reliability_range(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d, lo, hi)
+        assert r.count == o.count and _ok(r.R, o.sum), (lo, hi, r.R, o.sum)
+
+
+def test_edge_cases():
+    B = _B()
+    # no arcs: one empty vector, s and t apart
+    assert B.bat_ms_reliability(3, [], [], None, [], 0, 2, 1) == (0.0, 0)
+    # demand above every capacity sum
+    net = W.ms_bridge(11)
+    assert B.bat_ms_reliability(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, 11) == (0.0, 0)
+    # one-state arcs fix their capacity; 32 arcs and 32 nodes (the limits)
+    arcs = [(i, i + 1) for i in range(31)] + [(0, 31)]
+    sigma = [1] * 28 + [3] * 4
+    cap = [[2]] * 28 + [[0, 1, 2]] * 4
+    w = [[1.0]] * 28 + [[0.1, 0.2, 0.7]] * 4
+    for d in (1, 2, 3):
+        R, c = B.bat_ms_reliability(32, arcs, sigma, cap, w, 0, 17, d)
+        o = oracle.ms_reliability(32, arcs, sigma, cap, w, 0, 17, d)
+        assert c == o.count and _ok(R, o.sum), (d, R, o.sum)
+
+
+def test_workload_full_size_sampled():
+    """The benchmark's 3^18-vector workload: the whole sweep (arcs reordered
+    for the flow searches) equals the range sweep over the whole counter in
+    the caller's order, and spread ranges of it match the oracle."""
+    B = _B()
+    net = W.config_ms()
+    N = net.space
+    say("ms workload", net.name, N)
+    R, c = B.bat_ms_reliability(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d)
+    full = B.bat_ms_reliability_range(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d, 0, N)
+    assert c == full.count and _ok(R, full.R)
+    assert 0 < c < N
+    rng = np.random.default_rng(5)
+    for lo in sorted(int(x) for x in rng.integers(0, N - 70001, size=6)):
+        hi = lo + 70001
+        r = B.bat_ms_reliability_range(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d, lo, hi)
+        o = oracle.ms_reliability_range(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d, lo, hi)
+        assert r.count == o.count and _ok(r.R, o.sum), (lo, r.R, o.sum)
+    # the whole space on the oracle, in 64 equal ranges over the host cores,
+    # added in range order
+    from oracle import pbat
+    cuts = [N * j // 64 for j in range(65)]
+    outs, wall = pbat.run_ms_ranges(net, list(zip(cuts, cuts[1:])), processes=min(16, os.cpu_count() or 1))
+    hi = lo = 0.0
+    for r_, _, _ in outs:
+        hi, lo = pbat.dd_add(hi, lo, r_)
+    say("ms oracle whole space", wall, "s")
+    assert c == sum(o[1] for o in outs) and _ok(R, hi + lo), (R, hi + lo)
+    # a lower demand can only be met more often
+    R1, c1 = B.bat_ms_reliability(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, 1)
+    assert R1 >= R and c1 >= c
