@@ -26,12 +26,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs, 64 lanes each, 2.4 GHz peak engine clock; one int32
-# lane-op per lane per clock on the vector ALUs.  A bit-sliced lane-op
-# handles 32 state vectors, so the bit-operation peak is 32x the lane rate.
-CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
-PEAK_LANE_OPS = CUS * LANES * CLOCK_HZ            # 3.93e13 int32 lane-ops/s
-PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 1.26e15 bit-ops/s
+# MI355X: 256 CUs at a 2.4 GHz peak engine clock.  The vector ALUs of a CU
+# complete 128 32-bit lane-operations per clock: the chip's vector FP32 rate
+# (157.3 TFLOP/s counting an FMA as two) is 256 x 2.4e9 x 128 FMAs, and
+# integer add / xor chains issue at that rate too -- the library's VALU-rate
+# kernel retires 1.85 wave64 VALU instructions per CU per cycle by its own
+# SQ_INSTS_VALU and GRBM_GUI_ACTIVE counters (profiles/k_valu_peak_mi355x.md),
+# so one wave64 instruction per CU per clock is not the ceiling.  A
+# bit-sliced lane-op decides one arc for 32 state vectors, so the bit-op peak
+# is 32x the lane rate.
+CUS, CLOCK_HZ = 256, 2.4e9
+PEAK_LANE_OPS = CUS * 128 * CLOCK_HZ              # 7.86e13 int32 lane-ops/s
+PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 2.52e15 bit-ops/s
+BOX_CPU_SHARE = 16                                # host cores one GPU's box grants a job
 
 # Hardware counters of the enumeration kernel on this workload
 # (profiles/bat_fwd_jit_grid5x5_m40.md), keyed by the launch they were
@@ -80,6 +87,8 @@ def parse():
     ap.add_argument("--cpu-sample-log2", type=int, default=30,
                     help="log2 of the state vectors in the oracle's timed sample")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--valu-peak-only", action="store_true",
+                    help="only run the sustained integer VALU diagnostic (for counter runs) and exit")
     ap.add_argument("--copy-ref-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (the reference kernel "
                          "that scales the HBM byte counters) and exit")
@@ -97,27 +106,125 @@ def copy_reference(gib: float):
     print(json.dumps({"copy_reference_bytes_read": 4 * n, "copy_reference_bytes_written": 4 * n}), flush=True)
 
 
-def cpu_baseline(net, sample_log2: int):
-    """The CPU oracle (PBAT equal divisions over the host cores) on an evenly
-    spread sample of Eq. 6 divisions of the same workload."""
+def host_cpu():
+    """CPU model and how many host processes the oracle legs use: the box's
+    share for one GPU (16), fewer if fewer cores are visible."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    visible = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    procs = int(os.environ.get("BAT_BENCH_CPU_PROCS", "0")) or min(visible, BOX_CPU_SHARE)
+    return model, visible, procs
+
+
+def oracle_sample(net, sample_log2: int, procs: int, grad: bool = False, chi_log2: int = 17, p=None):
+    """The oracle (PBAT equal divisions, Eq. 6) on an evenly spread sample of
+    divisions of one network's counter: about 2^sample_log2 vectors."""
     from oracle import pbat
-    procs = int(os.environ.get("BAT_BENCH_CPU_PROCS", "0")) or min(os.cpu_count() or 1, 16)
-    chi = 1 << 17                                  # divisions of 2^23 vectors at m = 40
-    mu_log2 = net.m - 17
+    chi_log2 = min(chi_log2, net.m)
+    chi = 1 << chi_log2
+    mu_log2 = net.m - chi_log2
     k = max(1, 1 << max(0, sample_log2 - mu_log2))
     divs = pbat.spread_divisions(chi, k)
-    r = pbat.run(net.n, net.arcs, net.p, net.s, net.t, chi, divisions=divs, processes=procs)
-    return {
-        "value": r.vectors / r.wall_s / 1e9,
-        "unit": "Gvec/s",
-        "cores": r.processes,
-        "kind": "oracle",
-        "sample": f"{len(divs)} of {chi} equal divisions (Eq. 6) spread evenly over the 2^{net.m} "
-                  f"counter, {r.vectors} vectors, {r.wall_s:.1f} s wall on {r.processes} processes",
-        "inspections_per_vector": r.inspections / r.vectors,
-        "layers_per_vector": r.layers / r.vectors,
-        "projected_time_to_R_s": (1 << net.m) / (r.vectors / r.wall_s),
-    }
+    r = pbat.run(net.n, net.arcs, net.p if p is None else p, net.s, net.t, chi, divisions=divs, grad=grad,
+                 processes=procs)
+    return r, len(divs), chi
+
+
+def cpu_baselines(c2, c4, c3, sample_log2: int):
+    """The oracle as it stands, timed on the host cores, on bounded samples of
+    each workload, plus the work counters that set each roofline's
+    algorithmic work per vector."""
+    model, visible, procs = host_cpu()
+    out = {"cpu_model": model, "cores_visible": visible, "cores_used": procs}
+    # headline: the 5x5 grid, forward, all the cores the box grants
+    r, k, chi = oracle_sample(c2, sample_log2, procs)
+    out["c2"] = {
+        "value": r.vectors / r.wall_s / 1e9, "unit": "Gvec/s", "cores": r.processes, "kind": "oracle",
+        "sample": f"{k} of {chi} equal divisions (Eq. 6) spread evenly over the 2^{c2.m} counter, "
+                  f"{r.vectors} vectors, {r.wall_s:.1f} s wall on {r.processes} processes ({model})",
+        "projected_time_to_R_s": (1 << c2.m) / (r.vectors / r.wall_s),
+        "inspections_per_vector": r.inspections / r.vectors, "layers_per_vector": r.layers / r.vectors,
+        "connected_fraction": r.count / r.vectors}
+    # one core, comparable with the paper's single-thread BAT runs
+    r1, k1, chi1 = oracle_sample(c2, sample_log2 - 4, 1)
+    out["c2_single_core"] = {
+        "value": r1.vectors / r1.wall_s / 1e9, "unit": "Gvec/s", "cores": 1, "kind": "oracle",
+        "sample": f"{k1} of {chi1} divisions, {r1.vectors} vectors, {r1.wall_s:.1f} s ({model})",
+        "projected_time_to_R_s": (1 << c2.m) / (r1.vectors / r1.wall_s)}
+    # the differentiation workload: forward and forward + gradient
+    rf, kf, chif = oracle_sample(c4, sample_log2 - 2, procs)
+    rg, kg, chig = oracle_sample(c4, sample_log2 - 3, procs, grad=True)
+    out["c4"] = {
+        "value": rf.vectors / rf.wall_s / 1e9, "unit": "Gvec/s", "cores": rf.processes, "kind": "oracle",
+        "sample": f"{kf} of {chif} divisions, {rf.vectors} vectors, {rf.wall_s:.1f} s",
+        "inspections_per_vector": rf.inspections / rf.vectors, "connected_fraction": rf.count / rf.vectors}
+    out["c4_grad"] = {
+        "value": rg.vectors / rg.wall_s / 1e9, "unit": "Gvec/s", "cores": rg.processes, "kind": "oracle",
+        "sample": f"{kg} of {chig} divisions with all {c4.m} T1/T0 sums, {rg.vectors} vectors, "
+                  f"{rg.wall_s:.1f} s",
+        "inspections_per_vector": rg.inspections / rg.vectors}
+    # the batched workload: the oracle handles one probability vector per
+    # pass, so its rate in (vector, p-vector) pairs is its vector rate.
+    # Graphs are drawn with probability proportional to their 2^m vectors
+    # (systematic sampling on the cumulative count), so the mean of their
+    # counters estimates the workload's mean per vector.
+    import numpy as np
+    nets, pvs = c3
+    sizes = np.array([1 << g.m for g in nets], dtype=np.float64)
+    cum = np.cumsum(sizes) / sizes.sum()
+    picks = [int(np.searchsorted(cum, (j + 0.5) / 32)) for j in range(32)]
+    from oracle import pbat
+    jobs = []
+    for j, gi in enumerate(picks):
+        g = nets[gi]
+        chi = 1 << min(10, g.m)
+        for i in pbat.spread_divisions(chi, max(1, (1 << max(0, sample_log2 - 8)) >> (g.m - min(10, g.m)))):
+            lo, hi = pbat.division_bounds(g.m, chi, i)
+            jobs.append((g.n, g.arcs, pvs[gi][j % pvs[gi].shape[0]], g.s, g.t, lo, hi))
+    res, wall = pbat.run_ranges(jobs, procs)
+    vecs = sum(hi - lo for (*_, lo, hi) in jobs)
+    insp = sum(r[2] for r in res)
+    cnt = sum(r[1] for r in res)
+    out["c3"] = {
+        "value": vecs / wall / 1e9, "unit": "G(vector, p-vector) pairs/s", "cores": procs, "kind": "oracle",
+        "sample": f"32 of {len(nets)} graphs drawn by size, spread divisions of each, one p-vector each, "
+                  f"{vecs} vectors, {wall:.1f} s",
+        "inspections_per_vector": insp / vecs, "connected_fraction": cnt / vecs}
+    return out
+
+
+def ms_cpu_baseline(net, sample_log2: int, procs: int):
+    """The multi-state oracle on 256 equal ranges spread over the mixed-radix
+    counter, about 2^sample_log2 vectors in all."""
+    from oracle import pbat
+    N = net.space
+    per = max(1, (1 << sample_log2) // 256)
+    starts = [int((j + 0.5) * N / 256) for j in range(256)]
+    ranges = [(lo, min(N, lo + per)) for lo in starts]
+    outs, wall = pbat.run_ms_ranges(net, ranges, procs)
+    vecs = sum(hi - lo for lo, hi in ranges)
+    return {"value": vecs / wall / 1e9, "unit": "Gvec/s", "cores": procs, "kind": "oracle",
+            "sample": f"256 ranges of {per} vectors spread over the {N}-vector counter, {wall:.1f} s",
+            "projected_time_to_R_s": N / (vecs / wall),
+            "inspections_per_vector": sum(o[2] for o in outs) / vecs,
+            "connected_fraction": sum(o[1] for o in outs) / vecs}
+
+
+def roofline_alu(vectors: int, work_per_vector: float, kernel_s: float):
+    """Integer-ALU roofline of a bit-sliced sweep: algorithmic bit-operations
+    (the oracle's arc inspections per vector) per second against the bit-op
+    peak."""
+    ach = vectors * work_per_vector / kernel_s
+    return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_BIT_OPS / 1e12, "unit": "Tbitop/s",
+            "frac": ach / PEAK_BIT_OPS, "work_per_vector": work_per_vector,
+            "work_unit": "PLSA arc inspections (1 bit-op each)", "kernel_ms": kernel_s * 1e3}
 
 
 def batched_only():
@@ -149,6 +256,10 @@ def main():
         return
     if a.batched_only:
         batched_only()
+        return
+    if a.valu_peak_only:
+        import paper_2209_09711_amd as B
+        print(json.dumps({"valu_peak_lane_ops_per_s": B.bat_valu_peak()}), flush=True)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the enumeration would shard "
@@ -256,8 +367,21 @@ def main():
         "relaxations_per_sweep": li.relaxations,
     }
 
+    c4 = W.config4()
+    c3 = W.config3()
+    grad_c2_ms = None
     if not a.no_extras:
-        c4 = W.config4()
+        # the same sweep with all 40 gradients (the autotuner tuned it too)
+        B.bat_reliability_grad(net.n, arcs, net.p, net.s, net.t)
+        g2 = []
+        for _ in range(2):
+            B.bat_reliability_grad(net.n, arcs, net.p, net.s, net.t)
+            g2.append(B.bat_last_launch().kernel_ms)
+        grad_c2_ms = min(g2)
+        out["fwd_grad_vs_fwd_c2"] = {"workload": "5x5 grid, m=40, R + 40 gradients",
+                                     "fwd_kernel_ms": float(np.mean(kern_ms)), "fwd_grad_kernel_ms": grad_c2_ms,
+                                     "ratio": grad_c2_ms / float(np.mean(kern_ms)),
+                                     "grad_launch": launch_key(B.bat_last_launch())}
         B.bat_autotune(c4.n, c4.arcs, c4.p, c4.s, c4.t)
         B.bat_reliability(c4.n, c4.arcs, c4.p, c4.s, c4.t)          # warm both kernels
         B.bat_reliability_grad(c4.n, c4.arcs, c4.p, c4.s, c4.t)
@@ -276,7 +400,7 @@ def main():
     if not a.no_extras and not a.no_batched:
         # batched: one persistent launch vs the plain forward on every
         # (graph, probability vector) pair of the same workload
-        nets, pvs = W.config3()
+        nets, pvs = c3
         graphs = [(g.n, g.arc_array(), g.s, g.t) for g in nets]
         B.bat_reliability_batched(graphs, pvs)
         # autotune (one-time, reported separately): chain length and
@@ -284,10 +408,13 @@ def main():
         t0 = time.perf_counter()
         B.bat_autotune_batched(graphs, pvs)
         btune_s = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        Rb, cb = B.bat_reliability_batched(graphs, pvs)
-        bw = time.perf_counter() - t0
-        bk = B.bat_last_launch().kernel_ms
+        bks = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            Rb, cb = B.bat_reliability_batched(graphs, pvs)
+            bw = time.perf_counter() - t0
+            bks.append(B.bat_last_launch().kernel_ms)
+        bk = min(bks)
         t0 = time.perf_counter()
         pk = 0.0
         worst = 0.0
@@ -306,34 +433,84 @@ def main():
             "plain_wall_ms": pw * 1e3, "plain_kernel_ms_sum": pk,
             "speedup_wall": pw / bw, "max_rel_diff": worst}
 
+    msn = W.config_ms()
+    ms_out = None
+    if not a.no_extras:
+        # multi-state arcs: three capacity levels per arc, demand 2
+        B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, msn.d)
+        mks = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            Rm, cm = B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, msn.d)
+            mw = time.perf_counter() - t0
+            mks.append(B.bat_last_launch().kernel_ms)
+        ms_out = {"workload": f"random n={msn.n} m={msn.m} (seed 220909711/5), 3 capacity levels per arc, "
+                              f"demand {msn.d}, {msn.space} state vectors",
+                  "R": Rm, "count": cm, "kernel_ms": min(mks), "wall_ms": mw * 1e3,
+                  "value": msn.space / (min(mks) / 1e3) / 1e9, "unit": "Gvec/s"}
+        out["multistate"] = ms_out
+
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(net, a.cpu_sample_log2)
-        out["cpu_baseline"] = {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")}
-        out["cpu_baseline"]["projected_time_to_R_s"] = cpu["projected_time_to_R_s"]
+        cpu = cpu_baselines(net, c4, c3, a.cpu_sample_log2)
+        h = cpu["c2"]
+        out["cpu_baseline"] = {k: h[k] for k in ("value", "unit", "cores", "kind", "sample",
+                                                 "projected_time_to_R_s")}
+        out["cpu_baseline"]["cpu_model"] = cpu["cpu_model"]
+        out["cpu_baseline"]["cores_visible"] = cpu["cores_visible"]
+        out["cpu_baseline"]["cores_cap"] = "the host-core share of a one-GPU box (16)"
+        out["cpu_baseline_legs"] = {k: {kk: vv for kk, vv in cpu[k].items()
+                                        if kk not in ("inspections_per_vector", "layers_per_vector",
+                                                      "connected_fraction")}
+                                    for k in ("c2_single_core", "c4", "c4_grad", "c3")}
 
-    # roofline of the enumeration kernel: integer ALU bound (no HBM traffic
-    # per vector, no contraction).  Algorithmic work per state vector = the
-    # layered search's arc inspections (oracle-measured mean on the sample),
-    # one bit-operation each.
+    # rooflines: integer ALU bound (no HBM traffic per vector, no
+    # contraction).  Algorithmic work per state vector = the layered
+    # search's arc inspections (oracle-measured mean on each sample), one
+    # bit-operation each.
     kern_s = float(np.mean(kern_ms)) / 1e3
-    insp = cpu["inspections_per_vector"] if cpu else None
     # the sustained integer VALU rate this device reaches on independent
-    # add / xor chains (library diagnostic), as a second peak
+    # add / xor chains (library diagnostic)
     lane_peak = B.bat_valu_peak()
-    if insp is not None:
-        achieved = nvec * insp / kern_s
-        out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_BIT_OPS / 1e12,
-                           "unit": "Tbitop/s", "frac": achieved / PEAK_BIT_OPS,
-                           "traffic": MEASURED.get(launch_key(li_step), {}).get("traffic_bytes"),
-                           "valu_busy": MEASURED.get(launch_key(li_step), {}).get("valu_busy"),
-                           "valu_insts_per_vector": MEASURED.get(launch_key(li_step), {}).get("valu_insts_per_vector"),
-                           "salu_busy": MEASURED.get(launch_key(li_step), {}).get("salu_busy"),
-                           "lds_busy": MEASURED.get(launch_key(li_step), {}).get("lds_busy"),
-                           "launch": launch_key(li_step),
-                           "peak_measured": lane_peak * 32 / 1e12,
-                           "frac_measured": achieved / (lane_peak * 32) if lane_peak > 0 else None,
-                           "work_per_vector": insp, "work_unit": "PLSA arc inspections (1 bit-op each)"}
+    if cpu is not None:
+        insp = cpu["c2"]["inspections_per_vector"]
+        mk = MEASURED.get(launch_key(li_step), {})
+        rl = roofline_alu(nvec, insp, kern_s)
+        rl.update({"traffic": mk.get("traffic_bytes"), "valu_busy": mk.get("valu_busy"),
+                   "valu_insts_per_vector": mk.get("valu_insts_per_vector"), "salu_busy": mk.get("salu_busy"),
+                   "lds_busy": mk.get("lds_busy"), "launch": launch_key(li_step),
+                   "valu_rate_measured": lane_peak,
+                   "frac_of_measured_rate": nvec * insp / kern_s / (lane_peak * 32) if lane_peak > 0 else None})
+        out["roofline"] = rl
+        others = {}
+        if "fwd_grad_vs_fwd" in out:
+            f4 = out["fwd_grad_vs_fwd"]
+            n4 = 1 << c4.m
+            others["c4_fwd"] = roofline_alu(n4, cpu["c4"]["inspections_per_vector"], f4["fwd_kernel_ms"] / 1e3)
+            others["c4_fwd_grad"] = roofline_alu(n4, cpu["c4"]["inspections_per_vector"],
+                                                 f4["fwd_grad_kernel_ms"] / 1e3)
+        if grad_c2_ms:
+            others["c2_fwd_grad"] = roofline_alu(nvec, insp, grad_c2_ms / 1e3)
+        if "batched_vs_plain" in out:
+            bv = out["batched_vs_plain"]
+            nvb = sum(1 << g.m for g in c3[0])
+            # one connectivity verdict per vector serves all 32 p-vectors
+            others["c3_batched"] = roofline_alu(nvb, cpu["c3"]["inspections_per_vector"],
+                                                bv["batched_kernel_ms"] / 1e3)
+        if ms_out is not None:
+            mc = ms_cpu_baseline(msn, a.cpu_sample_log2 - 4, host_cpu()[2])
+            out["cpu_baseline_legs"]["multistate"] = {k: v for k, v in mc.items()
+                                                      if k not in ("inspections_per_vector", "connected_fraction")}
+            # one lane decides one vector (no bit-slicing): the work is the
+            # oracle's residual-edge looks in its augmenting-path searches,
+            # one 32-bit lane-op each, against the lane-op peak
+            ach = msn.space * mc["inspections_per_vector"] / (ms_out["kernel_ms"] / 1e3)
+            others["multistate"] = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                                    "unit": "Tlaneop/s", "frac": ach / PEAK_LANE_OPS,
+                                    "work_per_vector": mc["inspections_per_vector"],
+                                    "work_unit": "residual-edge looks of the augmenting-path searches "
+                                                 "(1 lane-op each)", "kernel_ms": ms_out["kernel_ms"]}
+        out["rooflines_other"] = others
     line = json.dumps(out)
     print(line, flush=True)
     if a.out:

@@ -451,8 +451,10 @@ int bat_last_launch(bat_launch_info *info);
  * 32-bit lane operations per second (*lane_ops_per_s), measured with a
  * kernel of independent add / xor chains (64 blocks of 256 threads per
  * CU; the best of three timed launches after a warm-up).  Sweeps are
- * bound by this rate; the nominal figure for 256 CUs at 2.4 GHz is
- * 256 x 64 x 2.4e9 = 3.93e13.  Blocks the calling thread for a few
+ * bound by this rate.  A CU issues up to 128 32-bit lane operations per
+ * clock (two wave64 VALU instructions), so the ceiling for 256 CUs at
+ * 2.4 GHz is 256 x 128 x 2.4e9 = 7.86e13; the kernel reaches about three
+ * quarters of it.  Blocks the calling thread for a few
  * milliseconds.  BAT_EINVAL for a NULL pointer, BAT_EDEVICE on a HIP error.
  */
 int bat_valu_peak(double *lane_ops_per_s);

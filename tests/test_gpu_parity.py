@@ -930,14 +930,15 @@ def test_launch_info_names_the_kernel():
 
 
 def test_valu_peak_diagnostic():
-    """The measured integer VALU rate is positive and within a factor of
-    two of one wave64 instruction per CU per clock (256 x 64 x 2.4e9), above
-    or below: the chip's 32-bit vector rate is quoted at 128 lanes per CU per
-    clock for packed FP32, and independent add / xor chains run faster than
-    64 (1.5x measured)."""
+    """The measured integer VALU rate is positive and below the chip's
+    32-bit vector issue limit, 128 lane-operations per CU per clock
+    (256 x 128 x 2.4e9 = 7.86e13 /s, the rate behind the vector FP32
+    figure), by at most rounding of the clock: the diagnostic's 16 VALU
+    instructions per trip were counted with SQ_INSTS_VALU, and it retires
+    about 1.9 wave64 instructions per CU per cycle."""
     B = _B()
     say("valu peak")
     r = B.bat_valu_peak()
-    nominal = 256 * 64 * 2.4e9
-    say("lane-ops/s", r, r / nominal)
-    assert 0.5 * nominal < r < 2.05 * nominal
+    limit = 256 * 128 * 2.4e9
+    say("lane-ops/s", r, r / limit)
+    assert 0.5 * limit < r < 1.05 * limit
