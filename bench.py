@@ -84,9 +84,13 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--batched-only", action="store_true",
                     help="only tune and time the batched launch on its workload (for profiling runs)")
+    ap.add_argument("--batched-pvec", type=int, default=0,
+                    help="with --batched-only: use only the first K probability vectors of each graph")
     ap.add_argument("--cpu-sample-log2", type=int, default=30,
                     help="log2 of the state vectors in the oracle's timed sample")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--multistate-only", action="store_true",
+                    help="only time the multi-state workload's sweep (for profiling runs)")
     ap.add_argument("--valu-peak-only", action="store_true",
                     help="only run the sustained integer VALU diagnostic (for counter runs) and exit")
     ap.add_argument("--copy-ref-gib", type=float, default=0.0,
@@ -227,8 +231,9 @@ def roofline_alu(vectors: int, work_per_vector: float, kernel_s: float):
             "work_unit": "PLSA arc inspections (1 bit-op each)", "kernel_ms": kernel_s * 1e3}
 
 
-def batched_only():
-    """The batched workload alone: tune, then time three launches."""
+def batched_only(pvec: int = 0):
+    """The batched workload alone: tune, then time three launches (pvec > 0:
+    only each graph's first pvec probability vectors)."""
     import numpy as np
     import torch
 
@@ -237,6 +242,8 @@ def batched_only():
 
     torch.cuda.set_device(0)
     nets, pvs = W.config3()
+    if pvec > 0:
+        pvs = [np.ascontiguousarray(pv[:pvec]) for pv in pvs]
     graphs = [(g.n, g.arc_array(), g.s, g.t) for g in nets]
     B.bat_autotune_batched(graphs, pvs)
     ks = []
@@ -255,7 +262,18 @@ def main():
         copy_reference(a.copy_ref_gib)
         return
     if a.batched_only:
-        batched_only()
+        batched_only(a.batched_pvec)
+        return
+    if a.multistate_only:
+        import bat_workloads as W
+        import paper_2209_09711_amd as B
+        msn = W.config_ms()
+        ks = []
+        for _ in range(3):
+            R, c = B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, msn.d)
+            ks.append(B.bat_last_launch().kernel_ms)
+        print(json.dumps({"workload": msn.name, "state_vectors": msn.space, "R": R, "count": c,
+                          "kernel_ms_all": ks}), flush=True)
         return
     if a.valu_peak_only:
         import paper_2209_09711_amd as B

@@ -352,6 +352,8 @@ int bat_ms_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arc
  *                      cover distant parts of the counter), 0 = counter
  *                      order; R and counts never depend on it beyond
  *                      floating-point rounding
+ *   "BAT_MS_RUN"       consecutive state vectors each lane of the
+ *                      multi-state sweep decides (0 = automatic)
  *   "BAT_WINDOW_TEST"  1 (default) = the graph-specialised sweeps (R, and
  *                      R with the gradient) test each window of 2048 iterations once, with all
  *                      11 word arcs up, and skips the chained blocks whose

@@ -71,7 +71,7 @@ int fail(int code, const char *fmt, ...)
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
         window_test{1}, block_waves{-1}, super_restart{-1}, simd_waves{-1}, keep_bottom{-1}, series{1},
-        grad_keep_bottom{2}, jit_flush_req{0};
+        grad_keep_bottom{2}, ms_run{0}, jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -93,6 +93,7 @@ struct Options {
         rd("BAT_KEEP_BOTTOM", keep_bottom);
         rd("BAT_SERIES", series);
         rd("BAT_GRAD_KEEP_BOTTOM", grad_keep_bottom);
+        rd("BAT_MS_RUN", ms_run);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -112,6 +113,7 @@ struct Options {
         if (!strcmp(k, "BAT_KEEP_BOTTOM")) return &keep_bottom;
         if (!strcmp(k, "BAT_SERIES")) return &series;
         if (!strcmp(k, "BAT_GRAD_KEEP_BOTTOM")) return &grad_keep_bottom;
+        if (!strcmp(k, "BAT_MS_RUN")) return &ms_run;
         if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
@@ -1731,12 +1733,14 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
     if (c_lo > c_hi || c_hi > N)
         return fail(BAT_EINVAL, "range [%llu, %llu) outside [0, %llu)", (unsigned long long)c_lo,
                     (unsigned long long)c_hi, (unsigned long long)N);
-    // Sweep order.  A whole space may take any arc order (R and the count
-    // are sums over every vector): arcs near s first, by breadth-first
-    // distance of their nearer end, so one search sweep reaches far.  A
-    // range keeps the caller's order, in which its indices are read.
+    // Slots: the kernel sweeps arcs in slot order, and slot 0 is the
+    // fastest-changing coordinate of its index.  A whole space may take any
+    // arc order (R and the count are sums over every vector): arcs near s
+    // first, by breadth-first distance of their nearer end, so one search
+    // sweep reaches far.  A range reads its indices in the caller's order,
+    // arc 0 most significant: slot j is arc m - 1 - j.
     std::vector<int> ord(m);
-    for (int i = 0; i < m; ++i) ord[i] = i;
+    for (int i = 0; i < m; ++i) ord[i] = whole ? i : m - 1 - i;
     if (whole && m > 1) {
         std::vector<int> dist(n, 1 << 30);
         std::vector<int> q{s};
@@ -1764,12 +1768,22 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
     K.t = (u32)t;
     K.d = (u32)d;
     K.directed = (flags & BAT_DIRECTED) ? 1u : 0u;
-    K.n_table = (u32)n_table;
+    K.n_table = (u32)n_table + (u32)((m <= 16 ? 16 : (m <= 24 ? 24 : 32)) - m);
     std::vector<int> first(m + 1, 0);
     for (int i = 0; i < m; ++i) first[i + 1] = first[i] + sigma[i];
-    std::vector<int32_t> capt(n_table);
-    std::vector<double> wt(n_table);
+    // the kernel instance's slot count; the slots past the last arc are
+    // one-state self-loops at s (capacity 0, probability 1): no-ops
+    const int slots = m <= 16 ? 16 : (m <= 24 ? 24 : 32);
+    std::vector<int32_t> capt(n_table + (slots - m));
+    std::vector<double> wt(n_table + (slots - m));
     u32 o = 0;
+    for (int j = m; j < slots; ++j) {
+        K.sig[j] = 1u;
+        K.off[j] = (u32)(n_table + (j - m));
+        K.u[j] = K.v[j] = (unsigned char)s;
+        capt[n_table + (j - m)] = 0;
+        wt[n_table + (j - m)] = 1.0;
+    }
     for (int j = 0; j < m; ++j) {
         const int i = ord[j];
         K.sig[j] = (u32)sigma[i];
@@ -1782,10 +1796,16 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
         }
         o += (u32)sigma[i];
     }
+    // slot 0's capacity nondecreasing in its state: the kernel's shortcuts
+    // along slot 0 are exact
+    K.warm = m > 0 ? 1u : 0u;
+    for (int k = 1; m > 0 && k < sigma[ord[0]]; ++k)
+        if (capt[k] < capt[k - 1]) K.warm = 0u;
     // launch shape: ~32K wavefront work items, each 64 runs of `run` indices
     const u64 span = c_hi - c_lo;
     const u64 target = 32768;
     K.run = std::max<u64>(1, (span + 64 * target - 1) / (64 * target));
+    if (opts().ms_run.load() > 0) K.run = (u64)opts().ms_run.load();
     K.n_items = span ? (span + 64 * K.run - 1) / (64 * K.run) : 0;
     K.c_lo = c_lo;
     K.c_hi = c_hi;
@@ -1796,9 +1816,10 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
     rc = thread_stream(D.id, st);
     if (rc) return rc;
     // workspace: input (cap | w tables) | partials | counts | output (res | count)
+    const size_t n_tab = capt.size();
     const size_t o_cap = 0;
-    const size_t o_w = align_up(o_cap + sizeof(int32_t) * (n_table + 1), 256);
-    const size_t in_bytes = align_up(o_w + sizeof(double) * (n_table + 1), 256);
+    const size_t o_w = align_up(o_cap + sizeof(int32_t) * (n_tab + 1), 256);
+    const size_t in_bytes = align_up(o_w + sizeof(double) * (n_tab + 1), 256);
     const u64 items = std::max<u64>(K.n_items, 1);
     const size_t o_part = in_bytes;
     const size_t o_pc = align_up(o_part + sizeof(double) * 2 * items, 256);
@@ -1811,8 +1832,8 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
     rc = scratch_reserve(D.id, st, total, out_host_off + out_bytes, S);
     if (rc) return rc;
     char *ws = S->dev;
-    memcpy(S->host + o_cap, capt.data(), sizeof(int32_t) * n_table);
-    memcpy(S->host + o_w, wt.data(), sizeof(double) * n_table);
+    memcpy(S->host + o_cap, capt.data(), sizeof(int32_t) * n_tab);
+    memcpy(S->host + o_w, wt.data(), sizeof(double) * n_tab);
     HIPCHK(hipMemcpyAsync(ws, S->host, in_bytes, hipMemcpyHostToDevice, st));
     K.cap = (const int *)(ws + o_cap);
     K.w = (const double *)(ws + o_w);
@@ -1839,7 +1860,7 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
     I.n_chunks = (int32_t)std::min<u64>(K.n_items, 0x7fffffff);
     I.chunk_log2 = -1;
     I.relaxations = m;
-    I.kernel_id = aot_kernel_id("k_ms_flow", m <= 16 ? 16 : 32, K.directed != 0);
+    I.kernel_id = aot_kernel_id("k_ms_flow", m <= 16 ? 16 : (m <= 24 ? 24 : 32), K.directed != 0);
     I.block_waves = bat::kWavesPerBlock;
     t_state.have_launch = true;
     memcpy(&R_hi, out, sizeof(double));

@@ -59,15 +59,16 @@ constexpr int kMsMaxDemand = 1024;
 constexpr int kMsMaxCapacity = 1 << 20;
 
 struct MsParams {
-    bat::u64 c_lo, c_hi;   // index range of the mixed-radix counter (arc 0 most significant)
+    bat::u64 c_lo, c_hi;   // index range of the mixed-radix counter (slot 0 least significant)
     bat::u64 run;          // consecutive indices per lane in a work item
     bat::u64 n_items;      // wavefront work items: item i covers [c_lo + 64 i run, c_lo + 64 (i+1) run)
     bat::u32 m, n, s, t, d, directed;
     bat::u32 n_table;      // sum of the state counts
-    bat::u32 sig[kMsMaxArcs];  // states of arc i
-    bat::u32 off[kMsMaxArcs];  // first table entry of arc i
+    bat::u32 warm;         // 1: slot 0's capacity is nondecreasing in its state
+    bat::u32 sig[kMsMaxArcs];  // states of the arc in slot i (sweep position i)
+    bat::u32 off[kMsMaxArcs];  // its first table entry
     unsigned char u[kMsMaxArcs], v[kMsMaxArcs];
-    const int *cap;        // [n_table] capacity of (arc, state), arc 0's states first
+    const int *cap;        // [n_table] capacity of (slot, state), slot 0's states first
     const double *w;       // [n_table] probability of (arc, state)
     double *part;          // [n_items][2] double-double partials
     bat::u64 *pcount;      // [n_items]

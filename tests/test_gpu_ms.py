@@ -101,6 +101,39 @@ def test_ranges_against_oracle():
         assert r.count == o.count and _ok(r.R, o.sum), (lo, hi, r.R, o.sum)
 
 
+@pytest.mark.parametrize("run", [1, 2, 3, 7, 64])
+def test_lane_runs(run):
+    """Lanes deciding several consecutive vectors: the shortcuts along the
+    fastest coordinate (settling its later states at once when a vector meets
+    the demand, passing the flow on when it does not) against the oracle,
+    with capacities that rise with the state (shortcuts on) and that do not
+    (shortcuts off), over whole spaces and ragged ranges."""
+    B = _B()
+    old = B.bat_get_option("BAT_MS_RUN")
+    try:
+        B.bat_set_option("BAT_MS_RUN", run)
+        for seed in range(6):
+            net = W.ms_random(7, 11, seed=300 + seed, d=1 + seed % 3)
+            if seed % 2:
+                net.cap = [[2, 0, 1]] * net.m           # not monotone in the state
+            say("ms run", run, seed)
+            R, c, o = _both(net, directed=seed % 3 == 1)
+            assert c == o.count and _ok(R, o.sum), (run, seed, R, o.sum)
+            N = net.space
+            for lo, hi in [(0, N), (5, N - 7), (N // 2, N // 2 + 999)]:
+                r = B.bat_ms_reliability_range(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d,
+                                               lo, hi)
+                oo = oracle.ms_reliability_range(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, net.d,
+                                                 lo, hi)
+                assert r.count == oo.count and _ok(r.R, oo.sum), (run, seed, lo, hi)
+        for seed in range(8):
+            net = W.ms_mixed(6, 9, seed=400 + seed)
+            R, c, o = _both(net)
+            assert c == o.count and _ok(R, o.sum), (run, "mixed", seed)
+    finally:
+        B.bat_set_option("BAT_MS_RUN", old)
+
+
 def test_edge_cases():
     B = _B()
     # no arcs: one empty vector, s and t apart
