@@ -385,6 +385,13 @@ int bat_ms_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arc
  *                      than s and t) into one relaxation with the AND of
  *                      their masks, which removes the node; 0 = relax
  *                      every arc.  Results are identical either way
+ *   "BAT_JIT_PROCS"    how many graph-specialised kernels bat_autotune
+ *                      compiles at once, each in a child process running
+ *                      the helper program bat_jitc from the library's
+ *                      directory (16 by default, at most 64; 0 = compile
+ *                      each in this process when first launched).  The
+ *                      code objects are those of an in-process compile:
+ *                      the helper uses this process's hiprtc library
  *   "BAT_JIT_FLUSH"    setting it to a nonzero value unloads every
  *                      graph-specialised kernel this process compiled or
  *                      loaded (after the current device finishes its work;
@@ -409,7 +416,9 @@ int bat_get_option(const char *key, int64_t *value);
  * sample of the counter range of this graph and caches the fastest choice
  * under the graph's structure; a later candidate must be at least 1%
  * faster to replace an earlier one.  The gradient sweep's arc order and
- * chain length are then tuned on their own, starting from the forward's.  Later calls on a graph of the same structure use it
+ * chain length are then tuned on their own, starting from the forward's.
+ * The candidates' specialised kernels are compiled side by side before
+ * they are timed (option "BAT_JIT_PROCS").  Later calls on a graph of the same structure use it
  * while "BAT_AUTOTUNE" is 1.  *best_ns_per_vector (may be NULL) receives the
  * best measured time per state vector.  Results never depend on the choice
  * beyond floating-point rounding; counts never change.

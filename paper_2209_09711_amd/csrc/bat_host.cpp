@@ -27,9 +27,14 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
+#include <dlfcn.h>
+#include <spawn.h>
 #include <sys/stat.h>
+#include <sys/wait.h>
 #include <unistd.h>
 
 #include "bat.h"
@@ -71,7 +76,7 @@ int fail(int code, const char *fmt, ...)
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
         window_test{1}, block_waves{-1}, super_restart{-1}, simd_waves{-1}, keep_bottom{-1}, series{1},
-        grad_keep_bottom{2}, ms_run{0}, jit_flush_req{0};
+        grad_keep_bottom{2}, ms_run{0}, jit_procs{16}, jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -94,6 +99,7 @@ struct Options {
         rd("BAT_SERIES", series);
         rd("BAT_GRAD_KEEP_BOTTOM", grad_keep_bottom);
         rd("BAT_MS_RUN", ms_run);
+        rd("BAT_JIT_PROCS", jit_procs);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -114,6 +120,7 @@ struct Options {
         if (!strcmp(k, "BAT_SERIES")) return &series;
         if (!strcmp(k, "BAT_GRAD_KEEP_BOTTOM")) return &grad_keep_bottom;
         if (!strcmp(k, "BAT_MS_RUN")) return &ms_run;
+        if (!strcmp(k, "BAT_JIT_PROCS")) return &jit_procs;
         if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
@@ -679,9 +686,18 @@ std::map<std::string, JitEntry> g_jit;
 
 // Drop every compiled kernel of this process (modules unloaded) after the
 // current device has finished its work.
+// Code objects compiled before their first launch (the autotuner compiles
+// its candidates' kernels side by side), by the key of their source text.
+std::mutex g_pre_mu;
+std::map<std::pair<uint64_t, uint64_t>, std::vector<char>> g_precompiled;
+
 void jit_flush()
 {
     (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lk(g_pre_mu);
+        g_precompiled.clear();
+    }
     std::lock_guard<std::mutex> lk(g_jit_mu);
     for (auto &kv : g_jit)
         if (kv.second.mod) (void)hipModuleUnload(kv.second.mod);
@@ -924,6 +940,152 @@ std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
     return s;
 }
 
+// One hiprtc compilation of a specialised kernel's source (no shared state:
+// several may run at once on host threads).
+const char *const kJitOpts[] = {"-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+
+std::string jit_key_text(const std::string &src, const std::string &arch)
+{
+    std::string keytext = src;
+    keytext += "\n//--offload-arch=" + arch;
+    for (const char *opt : kJitOpts) keytext += std::string("\n//") + opt;
+    return keytext;
+}
+
+bool jit_compile(const std::string &src, const std::string &arch, std::vector<char> &code, std::string &err)
+{
+    const std::string a = "--offload-arch=" + arch;
+    std::vector<const char *> o{a.c_str()};
+    for (const char *opt : kJitOpts) o.push_back(opt);
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "bat_jit.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+        err = "hiprtcCreateProgram failed";
+        return false;
+    }
+    hiprtcResult rc = hiprtcCompileProgram(prog, (int)o.size(), o.data());
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls + 1, '\0');
+        hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        err = std::string(hiprtcGetErrorString(rc)) + ": " + log.substr(0, 800);
+        return false;
+    }
+    size_t sz = 0;
+    hiprtcGetCodeSize(prog, &sz);
+    code.assign(sz, 0);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    return true;
+}
+
+// The compile helper (bat_jitc) installed beside this library, or "".
+std::string jitc_path()
+{
+    Dl_info di;
+    if (!dladdr((const void *)&jitc_path, &di) || !di.dli_fname) return "";
+    std::string p = di.dli_fname;
+    const size_t slash = p.rfind('/');
+    p = (slash == std::string::npos ? std::string(".") : p.substr(0, slash)) + "/bat_jitc";
+    return access(p.c_str(), X_OK) == 0 ? p : "";
+}
+
+// The file of the hiprtc library this process compiles with, or "".
+std::string hiprtc_path()
+{
+    Dl_info di;
+    if (!dladdr((const void *)&hiprtcCompileProgram, &di) || !di.dli_fname) return "";
+    return di.dli_fname;
+}
+
+// Compile the kernels of these (plan, gradient?, shape) launches that are
+// neither loaded nor on disk.  hiprtc runs one compilation at a time per
+// process, so they run in child processes of the compile helper, up to
+// option BAT_JIT_PROCS at once; their first launch then only loads the
+// code.  Whatever does not come back (no helper, a failed child) is
+// compiled in-process by that launch as usual.
+void jit_precompile(const DeviceInfo &D, const std::vector<std::tuple<const Plan *, bool, JitShape>> &want)
+{
+    const int64_t procs = std::min<int64_t>(opts().jit_procs.load(), 64);
+    if (procs < 1) return;
+    const std::string helper = jitc_path(), rtc = hiprtc_path();
+    if (helper.empty() || rtc.empty()) return;
+    struct Job {
+        std::string src;
+        CacheKey ck;
+        std::string src_path, out_path;
+        pid_t pid = -1;
+    };
+    std::vector<Job> jobs;
+    const std::string cdir = cache_dir();
+    for (const auto &w : want) {
+        Job j;
+        j.src = jit_source(*std::get<0>(w), std::get<1>(w), std::get<2>(w));
+        j.ck = cache_key(jit_key_text(j.src, D.arch));
+        {
+            std::lock_guard<std::mutex> lk(g_pre_mu);
+            if (g_precompiled.count({j.ck.h1, j.ck.h2})) continue;
+        }
+        if (!cdir.empty()) {
+            struct stat st;
+            if (stat(cache_path(cdir, j.ck).c_str(), &st) == 0) continue;  // on disk already
+        }
+        bool dup = false;
+        for (const Job &o : jobs) dup = dup || (o.ck.h1 == j.ck.h1 && o.ck.h2 == j.ck.h2);
+        if (!dup) jobs.push_back(std::move(j));
+    }
+    if (jobs.empty()) return;
+    const char *tenv = getenv("TMPDIR");
+    std::string dir = std::string(tenv && *tenv ? tenv : "/tmp") + "/bat_jitc.XXXXXX";
+    if (!mkdtemp(&dir[0])) return;
+    const std::string arch = "--offload-arch=" + D.arch;
+    for (size_t i0 = 0; i0 < jobs.size(); i0 += (size_t)procs) {
+        const size_t i1 = std::min(jobs.size(), i0 + (size_t)procs);
+        for (size_t i = i0; i < i1; ++i) {
+            Job &j = jobs[i];
+            j.src_path = dir + "/" + std::to_string(i) + ".hip";
+            j.out_path = dir + "/" + std::to_string(i) + ".co";
+            FILE *f = fopen(j.src_path.c_str(), "wb");
+            if (!f) continue;
+            const bool ok = fwrite(j.src.data(), 1, j.src.size(), f) == j.src.size();
+            if (fclose(f) != 0 || !ok) continue;
+            std::vector<char *> argv{(char *)helper.c_str(), (char *)rtc.c_str(), (char *)j.src_path.c_str(),
+                                     (char *)j.out_path.c_str(), (char *)arch.c_str()};
+            for (const char *opt : kJitOpts) argv.push_back((char *)opt);
+            argv.push_back(nullptr);
+            pid_t pid;
+            if (posix_spawn(&pid, helper.c_str(), nullptr, nullptr, argv.data(), environ) == 0) j.pid = pid;
+        }
+        for (size_t i = i0; i < i1; ++i) {
+            Job &j = jobs[i];
+            if (j.pid > 0) {
+                int st = 0;
+                pid_t r;
+                while ((r = waitpid(j.pid, &st, 0)) < 0 && errno == EINTR) {
+                }
+                std::vector<char> code;
+                if (r == j.pid && WIFEXITED(st) && WEXITSTATUS(st) == 0) {
+                    if (FILE *f = fopen(j.out_path.c_str(), "rb")) {
+                        char buf[1 << 16];
+                        size_t k;
+                        while ((k = fread(buf, 1, sizeof buf, f)) > 0) code.insert(code.end(), buf, buf + k);
+                        fclose(f);
+                    }
+                }
+                if (!code.empty()) {
+                    if (!cdir.empty()) cache_write(cache_path(cdir, j.ck), j.ck, code);
+                    std::lock_guard<std::mutex> lk(g_pre_mu);
+                    g_precompiled[{j.ck.h1, j.ck.h2}] = std::move(code);
+                }
+            }
+            unlink(j.src_path.c_str());
+            unlink(j.out_path.c_str());
+        }
+    }
+    rmdir(dir.c_str());
+}
+
 int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, hipFunction_t &fn, double &compile_ms,
             uint64_t &id)
 {
@@ -940,17 +1102,23 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
     }
     auto t0 = std::chrono::steady_clock::now();
     std::string src = jit_source(P, grad, sh);
-    std::string arch = "--offload-arch=" + D.arch;
-    const char *o[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    std::string keytext = src;
-    for (const char *opt : o) keytext += std::string("\n//") + opt;
-    const CacheKey ck = cache_key(keytext);
+    const CacheKey ck = cache_key(jit_key_text(src, D.arch));
     const std::string cdir = cache_dir();
     std::vector<char> code;
     // the kernel's identity: its machine code, so that edits which leave
     // the code alone (comments) keep it
     auto code_id = [&]() { return machine_code_id(code); };
-    if (!cdir.empty() && cache_read(cache_path(cdir, ck), ck, code)) {
+    bool pre = false;
+    {
+        std::lock_guard<std::mutex> lk(g_pre_mu);
+        auto pit = g_precompiled.find({ck.h1, ck.h2});
+        if (pit != g_precompiled.end()) {
+            code = std::move(pit->second);
+            g_precompiled.erase(pit);
+            pre = true;
+        }
+    }
+    if (!pre && !cdir.empty() && cache_read(cache_path(cdir, ck), ck, code)) {
         JitEntry e;
         e.id = id = code_id();
         if (hipModuleLoadData(&e.mod, code.data()) == hipSuccess &&
@@ -963,24 +1131,11 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
         if (e.mod) (void)hipModuleUnload(e.mod);
         (void)hipGetLastError();  // a stale or damaged entry: compile afresh
     }
-    hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, src.c_str(), "bat_jit.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
-        return fail(BAT_EDEVICE, "hiprtcCreateProgram failed");
-    hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof o / sizeof o[0]), o);
-    if (rc != HIPRTC_SUCCESS) {
-        size_t ls = 0;
-        hiprtcGetProgramLogSize(prog, &ls);
-        std::string log(ls + 1, '\0');
-        hiprtcGetProgramLog(prog, &log[0]);
-        hiprtcDestroyProgram(&prog);
-        return fail(BAT_EDEVICE, "hiprtc compile failed (%s): %.800s", hiprtcGetErrorString(rc), log.c_str());
+    if (!pre) {
+        std::string err;
+        if (!jit_compile(src, D.arch, code, err)) return fail(BAT_EDEVICE, "hiprtc compile failed (%s)", err.c_str());
+        if (!cdir.empty()) cache_write(cache_path(cdir, ck), ck, code);
     }
-    size_t sz = 0;
-    hiprtcGetCodeSize(prog, &sz);
-    code.assign(sz, 0);
-    hiprtcGetCode(prog, code.data());
-    hiprtcDestroyProgram(&prog);
-    if (!cdir.empty()) cache_write(cache_path(cdir, ck), ck, code);
     JitEntry e;
     e.id = id = code_id();
     HIPCHK(hipModuleLoadData(&e.mod, code.data()));
@@ -2267,6 +2422,39 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
             bc = c;
         }
     };
+    // compile the specialised kernels of candidates ahead of their runs, in
+    // parallel (their knobs resolved as a launch resolves them)
+    const std::string gkey = graph_key(n, m, arcs, s, t);
+    auto precompile = [&](const std::vector<std::pair<Cand, bool>> &cands) {
+        std::vector<Plan> plans(cands.size());
+        std::vector<std::tuple<const Plan *, bool, JitShape>> want;
+        for (size_t i = 0; i < cands.size(); ++i) {
+            const Cand &c = cands[i].first;
+            const bool grad = cands[i].second;
+            Request r{};
+            r.force_chunk_log2 = c.clog;
+            r.force_check = c.check;
+            r.force_jit = c.jit;
+            r.force_perm = c.perm;
+            r.force_chain = c.chain;
+            r.force_waves = c.waves;
+            r.force_super = c.super_restart;
+            r.force_simd = c.simd_waves;
+            r.force_keep = c.keep_bottom;
+            TuneChoice tc = choose(D, gkey, grad, &r);
+            if (tc.jit != 1) continue;
+            if (tc.perm < 0 || tc.perm >= kPermKinds) tc.perm = kDefaultPerm;
+            make_plan(n, m, arcs, s, t, plans[i], tc.perm);
+            want.emplace_back(&plans[i], grad, jit_shape(grad, tc.waves, tc.super_restart, tc.simd_waves, tc.keep_bottom));
+        }
+        jit_precompile(D, want);
+    };
+    {
+        std::vector<std::pair<Cand, bool>> first;
+        for (int i = 0; i < kPermKinds; ++i) first.push_back({{0, 1, 1, i, 3}, false});
+        for (int perm : {kDefaultPerm, 0}) first.push_back({{0, 1, 1, perm, 3}, true});
+        precompile(first);
+    }
     // stage 1: arc-to-bit order x chain length, specialised kernel,
     // automatic work-item size (the two interact); the default order first
     for (int i = 0; i < kPermKinds; ++i) {
@@ -2290,6 +2478,15 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
     // wavefronts and the super-block store (which takes LDS, so whole
     // 4-wavefront blocks wait for it)
     if (bc.jit != 0) {
+        {
+            std::vector<std::pair<Cand, bool>> shapes;
+            for (int sw : {5, 6, 0}) shapes.push_back({{bc.clog, bc.check, bc.jit, bc.perm, bc.chain, -1, -1, sw}, false});
+            shapes.push_back({{bc.clog, bc.check, bc.jit, bc.perm, bc.chain, -1, -1, -1, 2}, false});
+            shapes.push_back({{bc.clog, bc.check, bc.jit, bc.perm, bc.chain, 2, 0}, false});
+            shapes.push_back({{bc.clog, bc.check, bc.jit, bc.perm, bc.chain, 4, 1}, false});
+            shapes.push_back({{bc.clog, bc.check, bc.jit, bc.perm, 3}, true});
+            precompile(shapes);
+        }
         const Cand w2 = bc;
         // (-1 is the default: 6, or the compiler's budget for big plans)
         for (int sw : {5, 6, 0})

@@ -162,6 +162,70 @@ def test_jit_sources_compile(tmp_path, grad):
         B.bat_jit_source(3, [(0, 1), (1, 2)], 0, 2, perm=9)
 
 
+def _loaded_hiprtc():
+    """The hiprtc library file this process has mapped (the library's)."""
+    import paper_2209_09711_amd  # noqa: F401  (loads the library and its hiprtc)
+    with open("/proc/self/maps") as f:
+        for line in f:
+            path = line.split()[-1]
+            if os.path.basename(path).startswith("libhiprtc.so"):
+                return path
+    return None
+
+
+def test_jit_helper_matches_in_process_compile(tmp_path):
+    """The compile helper the autotuner runs side by side (bat_jitc, built
+    beside the library), given the hiprtc library this process uses, gives
+    byte for byte the code object of an in-process compile of the same
+    source with the same options, so a kernel's identity does not depend on
+    where it was compiled; a bad source fails with exit status 1."""
+    import subprocess
+    import bat_workloads as W
+    import paper_2209_09711_amd as B
+    rtc = _loaded_hiprtc()
+    assert rtc is not None
+    helper = os.path.join(os.path.dirname(B.LIB_PATH), "bat_jitc")
+    assert os.access(helper, os.X_OK)
+    net = W.config0()
+    src = B.bat_jit_source(net.n, net.arcs, net.s, net.t, perm=1)
+    opts = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    (tmp_path / "k.hip").write_text(src)
+    r = subprocess.run([helper, rtc, str(tmp_path / "k.hip"), str(tmp_path / "k.co"), *opts],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    via_helper = (tmp_path / "k.co").read_bytes()
+    assert via_helper[:4] == b"\x7fELF"
+    assert not (tmp_path / "k.co.part").exists()
+
+    h = ctypes.CDLL(rtc)
+    vp = ctypes.c_void_p
+    h.hiprtcCreateProgram.argtypes = [ctypes.POINTER(vp), ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int, vp, vp]
+    h.hiprtcCompileProgram.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p)]
+    h.hiprtcGetCodeSize.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    h.hiprtcGetCode.argtypes = [vp, ctypes.c_char_p]
+    h.hiprtcDestroyProgram.argtypes = [ctypes.POINTER(vp)]
+    prog = vp()
+    assert h.hiprtcCreateProgram(ctypes.byref(prog), src.encode(), b"bat_jit.hip", 0, None, None) == 0
+    argv = (ctypes.c_char_p * len(opts))(*[o.encode() for o in opts])
+    assert h.hiprtcCompileProgram(prog, len(opts), argv) == 0
+    size = ctypes.c_size_t()
+    assert h.hiprtcGetCodeSize(prog, ctypes.byref(size)) == 0
+    buf = ctypes.create_string_buffer(size.value)
+    assert h.hiprtcGetCode(prog, buf) == 0
+    h.hiprtcDestroyProgram(ctypes.byref(prog))
+    assert buf.raw == via_helper
+
+    (tmp_path / "bad.hip").write_text(src + "\nthis is not C++;\n")
+    r = subprocess.run([helper, rtc, str(tmp_path / "bad.hip"), str(tmp_path / "bad.co"), *opts],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1 and not (tmp_path / "bad.co").exists()
+    r = subprocess.run([helper], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    r = subprocess.run([helper, str(tmp_path / "no_such_lib.so"), str(tmp_path / "k.hip"), str(tmp_path / "x.co")],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+
+
 def test_flag_validation_without_device():
     """Unknown flag bits are rejected before any device work."""
     import paper_2209_09711_amd as B

@@ -638,6 +638,36 @@ def test_jit_disk_cache(tmp_path, monkeypatch):
     assert B.bat_get_option("BAT_JIT_FLUSH") == 0
 
 
+def test_autotune_compiles_side_by_side(tmp_path, monkeypatch):
+    """bat_autotune compiles its candidates' specialised kernels in helper
+    processes up front: tuning into an empty disk cache leaves an entry for
+    every arc order of the forward sweep and two of the gradient's, the
+    kernel a launch then runs is the one an in-process compile gives (the
+    same identity), and results match the frontier DP."""
+    import time
+    B = _B()
+    monkeypatch.setenv("BAT_JIT_CACHE_DIR", str(tmp_path))
+    monkeypatch.delenv("BAT_JIT_CACHE", raising=False)
+    net = W.random_connected(14, 28, seed=612, p_lo=0.5, p_hi=0.99)
+    Rd, cd = frontier_dp.reliability(net.n, net.arcs, net.p, net.s, net.t)
+    B.bat_set_option("BAT_JIT_FLUSH", 1)
+    with options(BAT_JIT_PROCS=16):
+        t0 = time.perf_counter()
+        B.bat_autotune(net.n, net.arcs, net.p, net.s, net.t)
+        say("autotune with helper processes: %.2f s" % (time.perf_counter() - t0))
+    assert len(list(tmp_path.glob("*.co"))) >= 6
+    with options(BAT_AUTOTUNE=0, BAT_JIT=1):
+        R1, c1 = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+        id1 = B.bat_last_launch().kernel_id
+    assert c1 == cd and rel_ok(R1, Rd)
+    monkeypatch.setenv("BAT_JIT_CACHE", "0")
+    B.bat_set_option("BAT_JIT_FLUSH", 1)
+    with options(BAT_JIT_PROCS=0, BAT_AUTOTUNE=0, BAT_JIT=1):
+        R2, c2 = B.bat_reliability(net.n, net.arcs, net.p, net.s, net.t)
+        assert B.bat_last_launch().kernel_id == id1
+    assert (R2, c2) == (R1, c1)
+
+
 # ------------------------------------------------------- directed, forward
 
 def _digraph(seed, n, m):
