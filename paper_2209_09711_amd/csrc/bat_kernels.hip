@@ -229,6 +229,7 @@ __global__ void __launch_bounds__(batk::batch_waves(NMAX) * bat::kWave) k_batche
     __shared__ double tb[kBatchMaxP][256];
     __shared__ double a4[kBatchMaxP][4];
     __shared__ double qlo[kBatchMaxP][1 << kBatchSegLog];
+    __shared__ double full[kBatchMaxP];  // F(~0): the mass of a word whose 32 vectors all connect
     __shared__ double wsum[kBatchWaves][kBatchMaxP][2];
     __shared__ u64 wcnt[kBatchWaves];
     __shared__ u64 s_item;
@@ -262,6 +263,15 @@ __global__ void __launch_bounds__(batk::batch_waves(NMAX) * bat::kWave) k_batche
             qlo[i >> kBatchSegLog][i & ((1u << kBatchSegLog) - 1u)] =
                 T[(u64)(i >> kBatchSegLog) * bat::kTablesFwd + bat::kQlo + (i & ((1u << kBatchSegLog) - 1u))];
         __syncthreads();
+        if (tid < P) {
+            // the same operations, in the same order, as a word of all ones
+            // takes through the tables below: either path gives the same bits
+            double F = a4[tid][0] * tb[tid][255];
+            F = __builtin_fma(a4[tid][1], tb[tid][255], F);
+            F = __builtin_fma(a4[tid][2], tb[tid][255], F);
+            full[tid] = __builtin_fma(a4[tid][3], tb[tid][255], F);
+        }
+        __syncthreads();
 
         const u64 iters = 1ull << E.ubits;
         const u64 seg = (item - E.item_begin) * kBatchWaves + w;
@@ -290,8 +300,19 @@ __global__ void __launch_bounds__(batk::batch_waves(NMAX) * bat::kWave) k_batche
                 if (g == iters - 1) V &= bat::edge_mask(0ull, chi, g, lane);
                 cnt += __popc(V);
                 if (__ballot(V != 0u) == 0ull) return;
-                const u32 b0 = V & 255u, b1 = (V >> 8) & 255u, b2 = (V >> 16) & 255u, b3 = V >> 24;
                 const u32 glo = (u32)(g & ((1ull << f) - 1ull));
+                // words that are all ones or all zeros (the five in-word arcs
+                // do not matter) need no byte-table reads: F is full or 0.
+                // Taken only when the whole wavefront's words are (a per-lane
+                // split measured no faster: the table path still issues)
+                if (__ballot(V != 0u && V != ~0u) == 0ull) {
+                    const double on = V ? 1.0 : 0.0;
+#pragma unroll
+                    for (int q = 0; q < kBatchMaxP; ++q)
+                        if ((u32)q < P) tot[q] = __builtin_fma(qlo[q][glo], on * full[q], tot[q]);
+                    return;
+                }
+                const u32 b0 = V & 255u, b1 = (V >> 8) & 255u, b2 = (V >> 16) & 255u, b3 = V >> 24;
                 // re-read the per-vector byte factors every iteration (held in
                 // registers they would need 256 VGPRs for 32 p-vectors): an
                 // opaque zero offset keeps the compiler from hoisting them
