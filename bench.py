@@ -245,15 +245,19 @@ def batched_only(pvec: int = 0):
     if pvec > 0:
         pvs = [np.ascontiguousarray(pv[:pvec]) for pv in pvs]
     graphs = [(g.n, g.arc_array(), g.s, g.t) for g in nets]
+    t0 = time.perf_counter()
     B.bat_autotune_batched(graphs, pvs)
+    tune_s = time.perf_counter() - t0
     ks = []
     for _ in range(3):
         B.bat_reliability_batched(graphs, pvs)
-        ks.append(B.bat_last_launch().kernel_ms)
+        li = B.bat_last_launch()
+        ks.append(li.kernel_ms)
     vec = sum(1 << g.m for g in nets)
     print(json.dumps({"workload": f"{len(nets)} random graphs x {pvs[0].shape[0]} p-vectors (seed 220909711/3)",
                       "state_vectors": vec, "batched_kernel_ms": float(np.min(ks)),
-                      "batched_kernel_ms_all": ks}), flush=True)
+                      "batched_kernel_ms_all": ks, "specialised": bool(li.specialised),
+                      "autotune_s": tune_s}), flush=True)
 
 
 def main():

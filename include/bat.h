@@ -218,10 +218,15 @@ int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes, const int3
  * Autotuner for the batched launch: runs this batch (same arguments as
  * bat_reliability_batched, results discarded) with each candidate number
  * of chained iteration bits (0, 3..6) and per-wavefront segment size
- * (2^4..2^6 iterations), and caches the fastest under the batch's
- * structure (graphs, terminals, n_pvec; not p).  Later batched calls with
- * that structure use it while "BAT_AUTOTUNE" is 1 and "BAT_CHAIN_LOG2" is
- * -1.  *best_kernel_ms (may be NULL) receives the best kernel time.
+ * (2^4..2^6 iterations), then with graph-specialised kernels for the
+ * graphs of at least m_max - 4, m_max - 2 or m_max arcs (m_max: the
+ * batch's largest arc count; compile time is not counted), and caches the
+ * fastest under the batch's structure (graphs, terminals, n_pvec; not p).
+ * A specialised candidate must be 2% faster than the best generic one.
+ * Later batched calls with that structure use the choice while
+ * "BAT_AUTOTUNE" is 1 ("BAT_CHAIN_LOG2" and "BAT_BATCH_JIT_ARCS", when not
+ * -1, override its parts).  *best_kernel_ms (may be NULL) receives the
+ * best kernel time.
  * Results never depend on the choice beyond floating-point rounding.
  */
 int bat_autotune_batched(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_offsets,
@@ -385,6 +390,17 @@ int bat_ms_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arc
  *                      than s and t) into one relaxation with the AND of
  *                      their masks, which removes the node; 0 = relax
  *                      every arc.  Results are identical either way
+ *   "BAT_BATCH_JIT_ARCS" batched form: graphs with at least this many arcs
+ *                      (and at least 2^(11+f) vectors, f the segment size)
+ *                      run their own graph-specialised kernel (compiled at
+ *                      run time, one per graph and p-vector group, side by
+ *                      side as for "BAT_JIT_PROCS"), the rest the generic
+ *                      persistent kernel, in the same call; 0 = none,
+ *                      -1 (default) = bat_autotune_batched's choice, else none
+ *   "BAT_BATCH_STREAMS" side streams (1..4, default 4) the specialised
+ *                      batched kernels are spread over, forked from and
+ *                      joined to the calling thread's stream, so that
+ *                      several run at once; 1 = the thread's stream only
  *   "BAT_JIT_PROCS"    how many graph-specialised kernels bat_autotune
  *                      compiles at once, each in a child process running
  *                      the helper program bat_jitc from the library's
@@ -472,9 +488,11 @@ int bat_valu_peak(double *lane_ops_per_s);
 
 /*
  * The source text of the graph-specialised kernel that the library hands
- * to hiprtc for this graph (flags: BAT_DIRECTED or 0): the forward sweep,
- * or the gradient sweep when grad != 0, with arc-to-counter-bit order
- * `perm` (0..3, as "BAT_PERM").
+ * to hiprtc for this graph (flags: BAT_DIRECTED or 0): the forward sweep
+ * (grad = 0), the gradient sweep (grad = 1), or the batched sweep of -grad
+ * probability vectors (grad = -1..-32; undirected only), with
+ * arc-to-counter-bit order `perm` (0..3, as "BAT_PERM"; the batched form
+ * always runs order 0).
  * Diagnostics only; needs no GPU.  The text is what hiprtc compiles: it
  * declares no headers.  buf (may be NULL) receives at most *len bytes
  * including the terminating NUL; *len is set to the size needed.

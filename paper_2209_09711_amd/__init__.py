@@ -380,14 +380,16 @@ def bat_autotune(n_nodes: int, arcs, p, s: int, t: int) -> float:
 
 
 def bat_jit_source(n_nodes: int, arcs, s: int, t: int, grad: bool = False, perm: int = 0,
-                   directed: bool = False) -> str:
-    """The hiprtc source of the graph-specialised kernel (diagnostics)."""
+                   directed: bool = False, batch_pvec: int = 0) -> str:
+    """The hiprtc source of the graph-specialised kernel (diagnostics);
+    batch_pvec > 0: the batched sweep of that many p-vectors."""
     a = _arcs(arcs)
     n = ctypes.c_uint64(0)
     f = _flags(directed)
-    _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, f, int(grad), perm, None, ctypes.byref(n)))
+    g = -int(batch_pvec) if batch_pvec else int(grad)
+    _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, f, g, perm, None, ctypes.byref(n)))
     buf = ctypes.create_string_buffer(n.value)
-    _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, f, int(grad), perm, buf, ctypes.byref(n)))
+    _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, f, g, perm, buf, ctypes.byref(n)))
     return buf.value.decode()
 
 

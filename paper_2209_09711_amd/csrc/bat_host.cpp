@@ -76,7 +76,7 @@ int fail(int code, const char *fmt, ...)
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
         window_test{1}, block_waves{-1}, super_restart{-1}, simd_waves{-1}, keep_bottom{-1}, series{1},
-        grad_keep_bottom{2}, ms_run{0}, jit_procs{16}, jit_flush_req{0};
+        grad_keep_bottom{2}, ms_run{0}, jit_procs{16}, batch_jit_arcs{-1}, batch_streams{4}, jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -100,6 +100,8 @@ struct Options {
         rd("BAT_GRAD_KEEP_BOTTOM", grad_keep_bottom);
         rd("BAT_MS_RUN", ms_run);
         rd("BAT_JIT_PROCS", jit_procs);
+        rd("BAT_BATCH_JIT_ARCS", batch_jit_arcs);
+        rd("BAT_BATCH_STREAMS", batch_streams);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -121,6 +123,8 @@ struct Options {
         if (!strcmp(k, "BAT_GRAD_KEEP_BOTTOM")) return &grad_keep_bottom;
         if (!strcmp(k, "BAT_MS_RUN")) return &ms_run;
         if (!strcmp(k, "BAT_JIT_PROCS")) return &jit_procs;
+        if (!strcmp(k, "BAT_BATCH_JIT_ARCS")) return &batch_jit_arcs;
+        if (!strcmp(k, "BAT_BATCH_STREAMS")) return &batch_streams;
         if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
@@ -542,11 +546,22 @@ struct Scratch {
 // thread's destructor makes no HIP call (the runtime may already be torn
 // down at process exit), so its streams, events and scratch come here
 // instead of being freed; the pool itself lives until the process ends.
+// Side streams of a thread on one device, for launches that may overlap
+// (the batched sweep's graph-specialised kernels), with the events that
+// fork them from and join them to the thread's stream.
+constexpr int kSideStreams = 4;
+struct SideStreams {
+    hipStream_t s[kSideStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSideStreams] = {};
+};
+
 struct ResourcePool {
     std::mutex mu;
     std::multimap<int, hipStream_t> streams;
     std::multimap<int, Scratch> scratch;
     std::vector<std::vector<hipEvent_t>> events;
+    std::multimap<int, SideStreams> side;
 };
 ResourcePool &pool()
 {
@@ -556,6 +571,7 @@ ResourcePool &pool()
 
 struct ThreadState {
     std::map<int, hipStream_t> streams;
+    std::map<int, SideStreams> side;
     std::map<int, Scratch> scratch;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool have_launch = false;
@@ -565,6 +581,7 @@ struct ThreadState {
         ResourcePool &P = pool();
         std::lock_guard<std::mutex> g(P.mu);
         for (auto &kv : streams) P.streams.emplace(kv.first, kv.second);
+        for (auto &kv : side) P.side.emplace(kv.first, kv.second);
         for (auto &kv : scratch)
             if (kv.second.dev || kv.second.host) P.scratch.emplace(kv.first, kv.second);
         if (ev[0]) P.events.emplace_back(ev, ev + 4);
@@ -590,6 +607,34 @@ int thread_stream(int dev, hipStream_t &s)
         it = t_state.streams.emplace(dev, st).first;
     }
     s = it->second;
+    return BAT_OK;
+}
+
+int side_streams(int dev, SideStreams *&out)
+{
+    auto it = t_state.side.find(dev);
+    if (it == t_state.side.end()) {
+        SideStreams S;
+        bool have = false;
+        {
+            ResourcePool &P = pool();
+            std::lock_guard<std::mutex> g(P.mu);
+            auto pit = P.side.find(dev);
+            if (pit != P.side.end()) {
+                S = pit->second;
+                P.side.erase(pit);
+                have = true;
+            }
+        }
+        if (!have) {
+            // default priority, like every stream of the library
+            for (int k = 0; k < kSideStreams; ++k) HIPCHK(hipStreamCreateWithFlags(&S.s[k], hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&S.fork, hipEventDisableTiming));
+            for (int k = 0; k < kSideStreams; ++k) HIPCHK(hipEventCreateWithFlags(&S.join[k], hipEventDisableTiming));
+        }
+        it = t_state.side.emplace(dev, S).first;
+    }
+    out = &it->second;
     return BAT_OK;
 }
 
@@ -869,7 +914,18 @@ JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int 
     return sh;
 }
 
-std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
+// batch_np > 0: instead of the forward or gradient sweep, the batched
+// sweep of batch_np probability vectors, in blocks of batch_jit_waves
+// wavefronts: 3 per SIMD (168 registers) keep the sweep loops free of
+// spills up to 16 p-vectors, beyond that 2 per SIMD (256 registers); at 3
+// per SIMD 32 accumulators spill inside the sweeps
+constexpr int batch_jit_waves(int np) { return np > 16 ? 8 : 12; }
+// p-vectors per specialised entry: 32 (blocks of 8 wavefronts) measured
+// faster than two entries of 16 (blocks of 12) on 256 graphs x 32
+// p-vectors, 18.7 against 19.4 ms: the closure then runs once
+constexpr int kBatchSpecP = 32;
+
+std::string jit_source(const Plan &P, bool grad, const JitShape &sh, int batch_np = 0)
 {
     std::string s;
     s.reserve(strlen(kDeviceSource) + 4096);
@@ -925,6 +981,11 @@ std::string jit_source(const Plan &P, bool grad, const JitShape &sh)
              "bat_grad_jit(bat::KParams P) {\n"
              "  __shared__ bat::LdsTables L; __shared__ bat::LdsGrad LG;\n"
              "  bat::sweep_kernel<bat::StaticClosure<JitGraph>, true>(P, L, &LG);\n}\n";
+    else if (batch_np > 0)
+        s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(bat::kWave * batch_jit_waves(batch_np)) +
+             ") bat_batch_jit(bat::KParams P) {\n"
+             "  __shared__ bat::LdsBatch<" + std::to_string(batch_np) + "> L;\n"
+             "  bat::batch_kernel<bat::StaticClosure<JitGraph>, " + std::to_string(batch_np) + ">(P, L);\n}\n";
     else if (grad)
         s += "extern \"C\" __global__ void __launch_bounds__(256) bat_grad_jit(bat::KParams P) {\n"
              "  __shared__ bat::LdsTables L; __shared__ bat::LdsGrad LG;\n"
@@ -1005,7 +1066,16 @@ std::string hiprtc_path()
 // option BAT_JIT_PROCS at once; their first launch then only loads the
 // code.  Whatever does not come back (no helper, a failed child) is
 // compiled in-process by that launch as usual.
+void jit_precompile_sources(const DeviceInfo &D, const std::vector<std::string> &sources);
+
 void jit_precompile(const DeviceInfo &D, const std::vector<std::tuple<const Plan *, bool, JitShape>> &want)
+{
+    std::vector<std::string> sources;
+    for (const auto &w : want) sources.push_back(jit_source(*std::get<0>(w), std::get<1>(w), std::get<2>(w)));
+    jit_precompile_sources(D, sources);
+}
+
+void jit_precompile_sources(const DeviceInfo &D, const std::vector<std::string> &sources)
 {
     const int64_t procs = std::min<int64_t>(opts().jit_procs.load(), 64);
     if (procs < 1) return;
@@ -1019,9 +1089,9 @@ void jit_precompile(const DeviceInfo &D, const std::vector<std::tuple<const Plan
     };
     std::vector<Job> jobs;
     const std::string cdir = cache_dir();
-    for (const auto &w : want) {
+    for (const std::string &src : sources) {
         Job j;
-        j.src = jit_source(*std::get<0>(w), std::get<1>(w), std::get<2>(w));
+        j.src = src;
         j.ck = cache_key(jit_key_text(j.src, D.arch));
         {
             std::lock_guard<std::mutex> lk(g_pre_mu);
@@ -1086,13 +1156,12 @@ void jit_precompile(const DeviceInfo &D, const std::vector<std::tuple<const Plan
     rmdir(dir.c_str());
 }
 
-int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, hipFunction_t &fn, double &compile_ms,
-            uint64_t &id)
+// The kernel `kname` of source `src`, loaded once per process under `key`:
+// from the precompiled table, else the disk cache, else compiled here.
+int jit_load(const DeviceInfo &D, const std::string &key, const std::string &src, const char *kname,
+             hipFunction_t &fn, double &compile_ms, uint64_t &id)
 {
     compile_ms = 0.0;
-    std::string key = std::to_string(D.id) + (grad ? " grad " : " fwd ") + std::to_string(sh.waves) +
-                      (sh.super_restart ? "s" : "") + (sh.keep_bottom ? (sh.bottom_lds ? "K" : "k") : "") + "/" +
-                      std::to_string(sh.simd_waves) + " " + P.structure;
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto it = g_jit.find(key);
     if (it != g_jit.end()) {
@@ -1101,7 +1170,6 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
         return BAT_OK;
     }
     auto t0 = std::chrono::steady_clock::now();
-    std::string src = jit_source(P, grad, sh);
     const CacheKey ck = cache_key(jit_key_text(src, D.arch));
     const std::string cdir = cache_dir();
     std::vector<char> code;
@@ -1110,7 +1178,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
     auto code_id = [&]() { return machine_code_id(code); };
     bool pre = false;
     {
-        std::lock_guard<std::mutex> lk(g_pre_mu);
+        std::lock_guard<std::mutex> lk2(g_pre_mu);
         auto pit = g_precompiled.find({ck.h1, ck.h2});
         if (pit != g_precompiled.end()) {
             code = std::move(pit->second);
@@ -1121,8 +1189,7 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
     if (!pre && !cdir.empty() && cache_read(cache_path(cdir, ck), ck, code)) {
         JitEntry e;
         e.id = id = code_id();
-        if (hipModuleLoadData(&e.mod, code.data()) == hipSuccess &&
-            hipModuleGetFunction(&e.fn, e.mod, grad ? "bat_grad_jit" : "bat_fwd_jit") == hipSuccess) {
+        if (hipModuleLoadData(&e.mod, code.data()) == hipSuccess && hipModuleGetFunction(&e.fn, e.mod, kname) == hipSuccess) {
             g_jit.emplace(key, e);
             fn = e.fn;
             compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1139,11 +1206,30 @@ int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, h
     JitEntry e;
     e.id = id = code_id();
     HIPCHK(hipModuleLoadData(&e.mod, code.data()));
-    HIPCHK(hipModuleGetFunction(&e.fn, e.mod, grad ? "bat_grad_jit" : "bat_fwd_jit"));
+    HIPCHK(hipModuleGetFunction(&e.fn, e.mod, kname));
     g_jit.emplace(key, e);
     fn = e.fn;
     compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return BAT_OK;
+}
+
+int jit_get(const DeviceInfo &D, const Plan &P, bool grad, const JitShape &sh, hipFunction_t &fn, double &compile_ms,
+            uint64_t &id)
+{
+    compile_ms = 0.0;
+    const std::string key = std::to_string(D.id) + (grad ? " grad " : " fwd ") + std::to_string(sh.waves) +
+                            (sh.super_restart ? "s" : "") + (sh.keep_bottom ? (sh.bottom_lds ? "K" : "k") : "") + "/" +
+                            std::to_string(sh.simd_waves) + " " + P.structure;
+    {
+        std::lock_guard<std::mutex> lk(g_jit_mu);
+        auto it = g_jit.find(key);
+        if (it != g_jit.end()) {
+            fn = it->second.fn;
+            id = it->second.id;
+            return BAT_OK;
+        }
+    }
+    return jit_load(D, key, jit_source(P, grad, sh), grad ? "bat_grad_jit" : "bat_fwd_jit", fn, compile_ms, id);
 }
 
 // ------------------------------------------------------------ autotune cache
@@ -2331,13 +2417,16 @@ int bat_jit_source(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t
     int rc = validate(n, m, arcs, nullptr, s, t);
     if (rc) return rc;
     if (perm < 0 || perm >= kPermKinds) return fail(BAT_EINVAL, "perm %d outside [0, %d)", perm, kPermKinds);
+    if (grad < -batk::kBatchMaxP || grad > 1) return fail(BAT_EINVAL, "grad %d outside [-%d, 1]", grad, batk::kBatchMaxP);
+    if (grad < 0 && (flags & BAT_DIRECTED)) return fail(BAT_EINVAL, "the batched sweep is undirected");
     Plan P;
     make_plan(n, m, arcs, s, t, P, perm, (flags & BAT_DIRECTED) != 0);
     Options &O = opts();
     const std::string src =
-        jit_source(P, grad != 0,
-                   jit_shape(grad != 0, (int)O.block_waves.load(), (int)O.super_restart.load(), (int)O.simd_waves.load(),
-                             (int)O.keep_bottom.load()));
+        grad < 0 ? jit_source(P, false, jit_shape(false, 4, 0, 0, 1), -grad)
+                 : jit_source(P, grad != 0,
+                              jit_shape(grad != 0, (int)O.block_waves.load(), (int)O.super_restart.load(),
+                                        (int)O.simd_waves.load(), (int)O.keep_bottom.load()));
     const uint64_t need = (uint64_t)src.size() + 1;
     const uint64_t have = *len;
     *len = need;
@@ -2549,6 +2638,7 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
 struct BatchTune {
     int chain = -1;  // -1: option BAT_CHAIN_LOG2 (-1 = 3)
     int seg = -1;    // -1: batk::kBatchSegLog
+    int jit_arcs = -1;  // graphs with at least this many arcs run graph-specialised (0: none; -1: option)
 };
 std::mutex g_btune_mu;
 std::map<std::string, BatchTune> g_btune;
@@ -2620,21 +2710,35 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         if (it != g_btune.end()) bt = it->second;
     }
     if (!force && opts().chain_log2.load() >= 0) bt.chain = (int)opts().chain_log2.load();
+    if (!force && opts().batch_jit_arcs.load() >= 0) bt.jit_arcs = (int)opts().batch_jit_arcs.load();
+    const int jit_arcs = bt.jit_arcs > 0 ? bt.jit_arcs : 0;
     // chained iteration bits (-1 = 3, 0 = none, 3..6)
     const int bchain = bt.chain < 0 ? 3 : (bt.chain >= 3 ? std::min(bt.chain, 6) : 0);
     const u32 bseg = bt.seg > 0 ? (u32)std::min(bt.seg, batk::kBatchSegLog) : (u32)batk::kBatchSegLog;
+    // graphs of at least jit_arcs arcs (and a full work item) get their own
+    // graph-specialised kernel, for at most kBatchSpecP p-vectors per entry;
+    // the rest share the generic persistent one
+    auto specialised = [&](const batk::BatchEntry &e) {
+        return jit_arcs > 0 && (int)e.m >= jit_arcs && e.ubits >= e.f && e.f >= 3;
+    };
     std::vector<batk::BatchEntry> ents;
     for (int32_t g = 0; g < n_graphs; ++g) {
         const Plan &P = plans[g];
         u32 m = (u32)P.m;
         u32 ubits = m > (u32)bat::kWordBits ? m - bat::kWordBits : 0u;
-        for (int32_t b = 0; b < n_pvec; b += batk::kBatchMaxP) {
+        batk::BatchEntry probe;
+        memset(&probe, 0, sizeof probe);
+        probe.m = m;
+        probe.ubits = ubits;
+        probe.f = std::min<u32>(ubits, bseg);
+        const int32_t per = specialised(probe) ? kBatchSpecP : batk::kBatchMaxP;
+        for (int32_t b = 0; b < n_pvec; b += per) {
             batk::BatchEntry e;
             memset(&e, 0, sizeof e);
             e.m = m;
             e.ubits = ubits;
             e.f = std::min<u32>(ubits, bseg);
-            e.P = (u32)std::min<int32_t>(batk::kBatchMaxP, n_pvec - b);
+            e.P = (u32)std::min<int32_t>(per, n_pvec - b);
             e.n_nodes = (u32)P.N;
             e.s = (u32)P.S;
             e.t = (u32)P.T;
@@ -2649,9 +2753,17 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
             ents.push_back(e);
         }
     }
-    std::stable_sort(ents.begin(), ents.end(),
-                     [](const batk::BatchEntry &a, const batk::BatchEntry &b) { return a.m > b.m; });
-    u64 n_items = 0, tab = 0;
+    // generic entries first (one queue), then the specialised ones; each
+    // part longest first
+    std::stable_sort(ents.begin(), ents.end(), [&](const batk::BatchEntry &a, const batk::BatchEntry &b) {
+        const bool sa = specialised(a), sb = specialised(b);
+        return sa != sb ? sb : a.m > b.m;
+    });
+    size_t n_gen = 0;
+    while (n_gen < ents.size() && !specialised(ents[n_gen])) ++n_gen;
+    nmax = 2;
+    for (size_t i = 0; i < n_gen; ++i) nmax = std::max(nmax, (int)ents[i].n_nodes);
+    u64 n_items = 0, n_gen_items = 0, tab = 0;
     std::vector<u64> item_start;
     std::vector<u32> pair_entry, pair_pv;
     std::vector<u64> entry_p_off;
@@ -2659,12 +2771,15 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     for (size_t i = 0; i < ents.size(); ++i) {
         batk::BatchEntry &e = ents[i];
         u64 iters = 1ull << e.ubits;
-        u64 per_item = (u64)batk::batch_waves(nmax) << e.f;
+        // a generic item is a block's worth of segments, a specialised one a
+        // single segment (one wavefront)
+        u64 per_item = i < n_gen ? (u64)batk::batch_waves(nmax) << e.f : 1ull << e.f;
         e.item_begin = n_items;
         e.n_items = (iters + per_item - 1) / per_item;
         e.tab_off = tab;
         item_start.push_back(n_items);
         n_items += e.n_items;
+        if (i < n_gen) n_gen_items = n_items;
         tab += (u64)e.P * bat::kTablesFwd;
         for (u32 q = 0; q < e.P; ++q) {
             pair_entry.push_back((u32)i);
@@ -2675,6 +2790,33 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     }
     item_start.push_back(n_items);
     const int64_t p_total = (int64_t)n_pvec * arc_offsets[n_graphs];
+
+    // the specialised kernels: one per (graph, p-vectors in the entry),
+    // compiled side by side before the first is loaded
+    std::vector<hipFunction_t> spec_fn(ents.size(), nullptr);
+    uint64_t spec_id = 0;
+    double spec_jit_ms = 0.0;
+    if (n_gen < ents.size()) {
+        const JitShape sh = jit_shape(false, 4, 0, 0, 1);
+        auto t0 = std::chrono::steady_clock::now();
+        std::vector<std::string> srcs(ents.size()), keys(ents.size()), todo;
+        for (size_t i = n_gen; i < ents.size(); ++i) {
+            keys[i] = std::to_string(D.id) + " batch" + std::to_string(ents[i].P) + " " + plans[ents[i].graph].structure;
+            srcs[i] = jit_source(plans[ents[i].graph], false, sh, (int)ents[i].P);
+            std::lock_guard<std::mutex> lk(g_jit_mu);
+            if (!g_jit.count(keys[i])) todo.push_back(srcs[i]);
+        }
+        if (!todo.empty()) jit_precompile_sources(D, todo);
+        for (size_t i = n_gen; i < ents.size(); ++i) {
+            const std::string &key = keys[i];
+            double ms = 0.0;
+            uint64_t id = 0;
+            rc = jit_load(D, key, srcs[i], "bat_batch_jit", spec_fn[i], ms, id);
+            if (rc) return rc;
+            spec_id = spec_id * 0x100000001b3ull + id;
+        }
+        spec_jit_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
 
     // device buffers (one stream-ordered allocation)
     size_t off = 0;
@@ -2718,16 +2860,72 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     memset(&BP, 0, sizeof BP);
     BP.entries = d_ent;
     BP.item_start = (const u64 *)(ws + o_ist);
-    BP.n_entries = (u32)ents.size();
+    BP.n_entries = (u32)n_gen;
     BP.check_every = opts().check_every.load() >= 2 ? 2u : 1u;
-    BP.n_items = n_items;
+    BP.n_items = n_gen_items;
     BP.prog = (const u32 *)(ws + o_prog);
     BP.tables = (const double *)(ws + o_tab);
     BP.part = (double *)(ws + o_part);
     BP.pcount = (u64 *)(ws + o_pc);
     BP.ctr = (unsigned long long *)(ws + o_ctr);
-    unsigned blocks = (unsigned)std::max<u64>(1, std::min<u64>((u64)D.cus, n_items));
-    HIPCHK(batk::batched_sweep(st, blocks, nmax, BP));
+    // the specialised kernels run on side streams forked from the thread's
+    // stream after the tables, so that small ones overlap; joined before
+    // the reduction
+    const size_t n_spec = ents.size() - n_gen;
+    SideStreams *SS = nullptr;
+    const int n_side = (int)std::min<int64_t>(std::min<int64_t>(opts().batch_streams.load(), kSideStreams), (int64_t)n_spec);
+    if (n_side > 1) {
+        rc = side_streams(D.id, SS);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(SS->fork, st));
+        for (int k = 0; k < n_side; ++k) HIPCHK(hipStreamWaitEvent(SS->s[k], SS->fork, 0));
+    }
+    const int window = opts().window_test.load() != 0 ? 1 : 0;
+    for (size_t i = n_gen; i < ents.size(); ++i) {
+        const batk::BatchEntry &e = ents[i];
+        bat::KParams K;
+        memset(&K, 0, sizeof K);
+        const u64 iters = 1ull << e.ubits;
+        K.c_lo = 0;
+        K.c_hi = 1ull << e.m;
+        K.g_first = 0;
+        K.g_last = iters - 1;
+        K.g_base = 0;
+        K.g_end = iters - 1;
+        K.chunk_iters = 1ull << e.f;  // one segment per work item
+        K.n_chunks = e.n_items;
+        K.chunk_mul = 1;
+        K.chunk_mask = ~0ull;
+        K.m = e.m;
+        K.ubits = e.ubits;
+        K.seg_log = e.f;
+        K.check_every = BP.check_every;
+        K.chain = e.chain;
+        K.ncol = 1;
+        K.window_test = (e.chain && window) ? 1u : 0u;
+        K.n_nodes = e.n_nodes;
+        K.s = e.s;
+        K.t = e.t;
+        K.tables = (const double *)(ws + o_tab) + e.tab_off;
+        K.part = (double *)(ws + o_part) + e.item_begin * batk::kBatchMaxP * 2;
+        K.pcount = (u64 *)(ws + o_pc) + e.item_begin;
+        const u64 wpb = (u64)batch_jit_waves((int)e.P);
+        const u64 blocks = std::min<u64>((u64)D.cus, (e.n_items + wpb - 1) / wpb);
+        void *args[] = {&K};
+        hipStream_t ls = n_side > 1 ? SS->s[(i - n_gen) % (size_t)n_side] : st;
+        HIPCHK(hipModuleLaunchKernel(spec_fn[i], (unsigned)blocks, 1, 1, (unsigned)(bat::kWave * wpb), 1, 1, 0, ls, args,
+                                     nullptr));
+    }
+    // the generic queue after the specialised kernels (the largest graphs)
+    // are queued: its persistent blocks then fill the CUs they leave
+    if (n_gen_items > 0) {
+        unsigned blocks = (unsigned)std::max<u64>(1, std::min<u64>((u64)D.cus, n_gen_items));
+        HIPCHK(batk::batched_sweep(st, blocks, nmax, BP));
+    }
+    for (int k = 0; n_side > 1 && k < n_side; ++k) {
+        HIPCHK(hipEventRecord(SS->join[k], SS->s[k]));
+        HIPCHK(hipStreamWaitEvent(st, SS->join[k], 0));
+    }
     HIPCHK(hipEventRecord(t_state.ev[2], st));
     HIPCHK(batk::batched_reduce(st, d_ent, (unsigned)ents.size(), (const double *)(ws + o_part),
                                 (const u64 *)(ws + o_pc), (u32)n_pvec, (double *)(ws + o_R), (u64 *)(ws + o_cnt)));
@@ -2739,7 +2937,8 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     bat_launch_info &I = t_state.info;
     memset(&I, 0, sizeof I);
     I.vectors = vectors;
-    I.specialised = 0;
+    I.specialised = n_gen < ents.size() ? 1 : 0;
+    I.jit_ms = spec_jit_ms;
     I.chunk_log2 = (int32_t)bseg;
     I.n_chunks = (int32_t)std::min<u64>(n_items, 0x7fffffff);
     {
@@ -2747,7 +2946,7 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         for (const Plan &pl : plans) nrel += pl.code.size();
         I.relaxations = (int32_t)nrel;
     }
-    I.kernel_id = aot_kernel_id("k_batched_dyn", (int)nmax, false);
+    I.kernel_id = aot_kernel_id("k_batched_dyn", (int)nmax, false) ^ spec_id;
     I.perm = -1;
     I.chain_log2 = (int32_t)bchain;
     I.check_every = 1;
@@ -2804,6 +3003,39 @@ extern "C" int bat_autotune_batched(int32_t n_graphs, const int32_t *n_nodes, co
                 bb = c;
             }
         }
+    // then graph-specialised kernels for the largest graphs (thresholds on
+    // the arc count: the largest, 2 and 4 below it), with the winning
+    // segment size and chain length; a threshold must win by 2% over none.
+    // (Smaller segments for the specialised graphs, which spread a graph
+    // over more wavefronts, measured slower on 256 graphs x 32 p-vectors.)
+    if (bb.chain != 0) {
+        int32_t m_max = 0;
+        for (int32_t g = 0; g < n_graphs; ++g) m_max = std::max(m_max, arc_offsets[g + 1] - arc_offsets[g]);
+        const double base = best;
+        const BatchTune gen = bb;
+        for (int arcs_min : {m_max - 4, m_max - 2, m_max}) {
+            if (arcs_min < bat::kWordBits + 3) continue;
+            BatchTune c = gen;
+            c.jit_arcs = arcs_min;
+            double ms = 1e300;
+            for (int rep = 0; rep < 3; ++rep) {
+                rc = batched_impl(n_graphs, n_nodes, arc_offsets, arcs, s, t, n_pvec, p, R.data(), cnt.data(), &c);
+                if (rc) return rc;
+                bat_launch_info li;
+                rc = bat_last_launch(&li);
+                if (rc) return rc;
+                if (rep > 0) ms = std::min(ms, li.kernel_ms);
+            }
+            if (verbose)
+                fprintf(stderr, "bat_autotune_batched: seg_log2=%d chain=%d specialised from %d arcs -> %.3f ms\n",
+                        c.seg, c.chain, arcs_min, ms);
+            if (ms < best && ms < base * 0.98) {
+                best = ms;
+                bb = c;
+            }
+        }
+        if (bb.jit_arcs < 0) bb.jit_arcs = 0;  // tuned: none
+    }
     {
         std::lock_guard<std::mutex> lk(g_btune_mu);
         g_btune[batch_key(D.id, n_graphs, n_nodes, arc_offsets, arcs, s, t, n_pvec)] = bb;

@@ -15,6 +15,8 @@ constexpr int batch_waves(int nmax) { return nmax <= 16 ? 12 : 8; }
 constexpr int kBatchWavesMax = 12;
 constexpr int kBatchMaxP = 32;                  // probability vectors per entry
 constexpr int kBatchSegLog = 6;                 // iterations per wavefront work unit: 2^f
+static_assert(kBatchMaxP == bat::kBatchCols, "partial slot layout of the batched sweeps");
+static_assert((1 << kBatchSegLog) <= bat::kBatchQlo, "Q_lo table of the specialised batched sweep");
 
 // One (graph, group of <= 32 probability vectors).  Its work is split into
 // items of batch_waves(nmax) * 2^f iterations; items of all entries form one

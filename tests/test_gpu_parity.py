@@ -839,6 +839,39 @@ def test_batched_vs_plain_and_oracle(n_pvec):
             assert cnt[g] == cd and rel_ok(R[g, j], Rd), (g, j)
 
 
+@pytest.mark.parametrize("n_pvec,jit_arcs,window,streams",
+                         [(1, 14, 1, 4), (7, 18, 1, 4), (32, 14, 1, 4), (45, 20, 1, 2), (9, 14, 0, 1)])
+def test_batched_specialised_kernels(n_pvec, jit_arcs, window, streams):
+    """Graphs with at least jit_arcs arcs run graph-specialised batched
+    kernels (on up to `streams` side streams), the rest the generic launch,
+    in the same call: counts equal to the generic launch's, R within
+    rounding of it, and every p-vector index against the frontier DP (more
+    than 32 p-vectors split into entries)."""
+    B = _B()
+    graphs, pblocks = _batch_inputs(900 + n_pvec, 10, n_pvec)
+    rng = np.random.default_rng(950 + n_pvec)
+    for n, m in [(12, 20), (14, 24), (16, 26), (10, 16), (13, 22)]:
+        net = W.random_connected(n, m, seed=int(rng.integers(1 << 30)))
+        s, t = (int(x) for x in rng.choice(n, 2, replace=False))
+        graphs.append((net.n, net.arcs, s, t))
+        pblocks.append(rng.uniform(0.3, 1.0, size=(n_pvec, m)))
+    with options(BAT_BATCH_JIT_ARCS=0):
+        R0, c0 = B.bat_reliability_batched(graphs, pblocks)
+        assert B.bat_last_launch().specialised == 0
+    with options(BAT_BATCH_JIT_ARCS=jit_arcs, BAT_WINDOW_TEST=window, BAT_BATCH_STREAMS=streams):
+        say("batched specialised from", jit_arcs, "arcs,", n_pvec, "p-vectors")
+        R, c = B.bat_reliability_batched(graphs, pblocks)
+        assert B.bat_last_launch().specialised == 1
+        R2, c2 = B.bat_reliability_batched(graphs, pblocks)
+    assert np.array_equal(R, R2) and np.array_equal(c, c2)       # deterministic
+    assert np.array_equal(c, c0)
+    assert np.allclose(R, R0, rtol=1e-12, atol=0)
+    for g, (n, arcs, s_, t_) in enumerate(graphs):
+        for j in sorted({g % n_pvec, n_pvec - 1}):
+            Rd, cd = frontier_dp.reliability(n, arcs, pblocks[g][j], s_, t_)
+            assert c[g] == cd and rel_ok(R[g, j], Rd), (g, j, R[g, j], Rd)
+
+
 @pytest.mark.parametrize("k", [0, 3, 4, 5, 6])
 def test_batched_chain_lengths(k):
     """Warm-started chains in the batched launch: counts exact, R equal to the
