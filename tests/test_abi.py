@@ -162,6 +162,42 @@ def test_jit_sources_compile(tmp_path, grad):
         B.bat_jit_source(3, [(0, 1), (1, 2)], 0, 2, perm=9)
 
 
+@pytest.mark.skipif(_hipcc() is None, reason="hipcc not installed")
+@pytest.mark.parametrize("npv", [1, 16, 32])
+def test_batch_jit_sources_compile(tmp_path, npv):
+    """The graph-specialised batched sweep compiles for gfx950 for 1, 16 and
+    32 p-vectors, with its 32 accumulators in blocks of 8 wavefronts and
+    fewer in blocks of 12, and no scratch access inside the sweep loops."""
+    import subprocess
+    import bat_workloads as W
+    import paper_2209_09711_amd as B
+    nets, _ = W.config3(n_graphs=40, n_pvec=1)
+    net = max(nets, key=lambda g: (g.m, g.n))
+    src = B.bat_jit_source(net.n, net.arcs, net.s, net.t, batch_pvec=npv)
+    assert "bat_batch_jit" in src and f"LdsBatch<{npv}>" in src
+    assert f"__launch_bounds__({64 * (8 if npv > 16 else 12)})" in src
+    f = tmp_path / "b.hip"
+    f.write_text("#include <hip/hip_runtime.h>\n" + src)
+    out = tmp_path / "b.s"
+    r = subprocess.run([_hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+                        "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-S", "-o", str(out), str(f)],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    asm = out.read_text()
+    depth, inner = 0, []
+    for line in asm.splitlines():
+        if re.match(r"^(\.LBB\d+_\d+:|; %bb\.\d+:)", line):
+            mm = re.search(r"Depth=(\d+)", line)
+            depth = int(mm.group(1)) if mm else 0
+        if "scratch_" in line and depth >= 2:
+            inner.append(line.strip())
+    assert not inner, inner[:4]
+    with pytest.raises(B.BatError):
+        B.bat_jit_source(net.n, net.arcs, net.s, net.t, batch_pvec=33)
+    with pytest.raises(B.BatError):
+        B.bat_jit_source(net.n, net.arcs, net.s, net.t, batch_pvec=4, directed=True)
+
+
 def _loaded_hiprtc():
     """The hiprtc library file this process has mapped (the library's)."""
     import paper_2209_09711_amd  # noqa: F401  (loads the library and its hiprtc)
