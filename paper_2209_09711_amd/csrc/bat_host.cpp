@@ -1060,14 +1060,15 @@ std::string hiprtc_path()
     return di.dli_fname;
 }
 
-// Compile the kernels of these (plan, gradient?, shape) launches that are
-// neither loaded nor on disk.  hiprtc runs one compilation at a time per
-// process, so they run in child processes of the compile helper, up to
-// option BAT_JIT_PROCS at once; their first launch then only loads the
-// code.  Whatever does not come back (no helper, a failed child) is
-// compiled in-process by that launch as usual.
+// Compile the kernels of these sources that are neither precompiled nor
+// on disk.  hiprtc runs one compilation at a time per process, so they run
+// in child processes of the compile helper, up to option BAT_JIT_PROCS at
+// once; their first launch then only loads the code.  Whatever does not
+// come back (no helper, a failed child) is compiled in-process by that
+// launch as usual.
 void jit_precompile_sources(const DeviceInfo &D, const std::vector<std::string> &sources);
 
+// The same for the kernels of these (plan, gradient?, shape) launches.
 void jit_precompile(const DeviceInfo &D, const std::vector<std::tuple<const Plan *, bool, JitShape>> &want)
 {
     std::vector<std::string> sources;
