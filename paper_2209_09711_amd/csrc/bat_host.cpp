@@ -2010,12 +2010,12 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
     K.t = (u32)t;
     K.d = (u32)d;
     K.directed = (flags & BAT_DIRECTED) ? 1u : 0u;
-    K.n_table = (u32)n_table + (u32)((m <= 16 ? 16 : (m <= 24 ? 24 : 32)) - m);
+    K.n_table = (u32)n_table + (u32)(batk::ms_slots(m) - m);
     std::vector<int> first(m + 1, 0);
     for (int i = 0; i < m; ++i) first[i + 1] = first[i] + sigma[i];
     // the kernel instance's slot count; the slots past the last arc are
     // one-state self-loops at s (capacity 0, probability 1): no-ops
-    const int slots = m <= 16 ? 16 : (m <= 24 ? 24 : 32);
+    const int slots = batk::ms_slots(m);
     std::vector<int32_t> capt(n_table + (slots - m));
     std::vector<double> wt(n_table + (slots - m));
     u32 o = 0;
@@ -2102,7 +2102,7 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
     I.n_chunks = (int32_t)std::min<u64>(K.n_items, 0x7fffffff);
     I.chunk_log2 = -1;
     I.relaxations = m;
-    I.kernel_id = aot_kernel_id("k_ms_flow", m <= 16 ? 16 : (m <= 24 ? 24 : 32), K.directed != 0);
+    I.kernel_id = aot_kernel_id("k_ms_flow", batk::ms_slots(m), K.directed != 0);
     I.block_waves = bat::kWavesPerBlock;
     t_state.have_launch = true;
     memcpy(&R_hi, out, sizeof(double));

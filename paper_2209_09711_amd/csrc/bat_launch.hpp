@@ -54,6 +54,9 @@ hipError_t batched_reduce(hipStream_t st, const BatchEntry *entries, unsigned n_
 
 // ---- multi-state arcs (bat_ms.hip)
 constexpr int kMsMaxArcs = 32;     // arc masks and reach sets are 32-bit words
+// slots of the kernel instance that sweeps m arcs (the rest padded): 16,
+// 20, 24 or 32; up to 20 slots the kernel fits 4 wavefronts per SIMD
+constexpr int ms_slots(int m) { return m <= 16 ? 16 : m <= 20 ? 20 : m <= 24 ? 24 : 32; }
 constexpr int kMsMaxNodes = 32;
 constexpr int kMsMaxStates = 32;   // per arc
 constexpr int kMsMaxTable = 1024;  // sum of the arcs' state counts (LDS tables)

@@ -39,7 +39,7 @@
 // loops at s (capacity 0, probability 1), which change nothing, so every
 // sweep is straight-line code over MM slots with no test of the arc count.
 // Every per-slot value (state, residual capacities) is a register: every
-// loop over slots is unrolled to the kernel's bound MM (16, 24 or 32
+// loop over slots is unrolled to the kernel's bound MM (16, 20, 24 or 32
 // slots), and node sets are
 // indexed by shifts only.  Pr(X) is the product of the other slots'
 // probabilities, formed when they change, times slot 0's.  Sums:
@@ -52,8 +52,11 @@
 using bat::u32;
 using bat::u64;
 
+// Up to 20 slots the per-slot registers (state, two residuals) leave room
+// for 4 wavefronts per SIMD (128 VGPRs); the compiler is held to that.
 template <int MM>
-__global__ void __launch_bounds__(256) k_ms_flow(batk::MsParams P)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MM <= 20 ? 4 : 1, MM <= 20 ? 4 : 8)))
+k_ms_flow(batk::MsParams P)
 {
     __shared__ int capt[batk::kMsMaxTable + batk::kMsMaxArcs];
     __shared__ double wt[batk::kMsMaxTable + batk::kMsMaxArcs];
@@ -223,6 +226,7 @@ __global__ void __launch_bounds__(256) k_ms_flow(batk::MsParams P)
 }
 
 template __global__ void k_ms_flow<16>(batk::MsParams);
+template __global__ void k_ms_flow<20>(batk::MsParams);
 template __global__ void k_ms_flow<24>(batk::MsParams);
 template __global__ void k_ms_flow<32>(batk::MsParams);
 
@@ -231,9 +235,12 @@ namespace batk {
 hipError_t ms_sweep(hipStream_t st, unsigned blocks, const MsParams &P)
 {
     const dim3 g(blocks), b(bat::kBlock);
-    if (P.m <= 16) hipLaunchKernelGGL(k_ms_flow<16>, g, b, 0, st, P);
-    else if (P.m <= 24) hipLaunchKernelGGL(k_ms_flow<24>, g, b, 0, st, P);
-    else hipLaunchKernelGGL(k_ms_flow<32>, g, b, 0, st, P);
+    switch (ms_slots((int)P.m)) {
+    case 16: hipLaunchKernelGGL(k_ms_flow<16>, g, b, 0, st, P); break;
+    case 20: hipLaunchKernelGGL(k_ms_flow<20>, g, b, 0, st, P); break;
+    case 24: hipLaunchKernelGGL(k_ms_flow<24>, g, b, 0, st, P); break;
+    default: hipLaunchKernelGGL(k_ms_flow<32>, g, b, 0, st, P); break;
+    }
     return hipGetLastError();
 }
 

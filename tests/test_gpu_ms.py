@@ -152,6 +152,35 @@ def test_edge_cases():
         assert c == o.count and _ok(R, o.sum), (d, R, o.sum)
 
 
+@pytest.mark.parametrize("m", [16, 17, 20, 21, 24, 25])
+def test_slot_instances(m):
+    """Arc counts at the edges of the kernel instances (16, 20, 24 and 32
+    slots, the rest padded with no-op slots): against the oracle, with
+    eight three-level arcs and the rest fixed at one state."""
+    B = _B()
+    rng = np.random.default_rng(600 + m)
+    n = 12
+    arcs = [(i, i + 1) for i in range(n - 1)]
+    while len(arcs) < m:
+        u, v = (int(x) for x in rng.choice(n, 2, replace=False))
+        arcs.append((u, v))
+    multi = set(int(x) for x in rng.choice(m, 8, replace=False))
+    sigma = [3 if i in multi else 1 for i in range(m)]
+    cap = [[0, 1, 2] if i in multi else [int(rng.integers(1, 3))] for i in range(m)]
+    w = []
+    for i in range(m):
+        if i in multi:
+            q = rng.dirichlet([1.0, 1.0, 1.0])
+            w.append([float(x) for x in q])
+        else:
+            w.append([1.0])
+    for d in (1, 2, 3):
+        say("ms slots", m, "d", d)
+        R, c = B.bat_ms_reliability(n, arcs, sigma, cap, w, 0, n - 1, d)
+        o = oracle.ms_reliability(n, arcs, sigma, cap, w, 0, n - 1, d)
+        assert c == o.count and _ok(R, o.sum), (m, d, R, o.sum)
+
+
 def test_workload_full_size_sampled():
     """The benchmark's 3^18-vector workload: the whole sweep (arcs reordered
     for the flow searches) equals the range sweep over the whole counter in
