@@ -2836,6 +2836,14 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     const size_t o_R = take(sizeof(double) * (size_t)n_graphs * n_pvec);
     const size_t o_cnt = take(sizeof(u64) * (size_t)n_graphs);
     char *ws = nullptr;
+    // side streams for the specialised kernels (before anything is queued)
+    const size_t n_spec = ents.size() - n_gen;
+    SideStreams *SS = nullptr;
+    const int n_side = (int)std::min<int64_t>(std::min<int64_t>(opts().batch_streams.load(), kSideStreams), (int64_t)n_spec);
+    if (n_side > 1) {
+        rc = side_streams(D.id, SS);
+        if (rc) return rc;
+    }
     HIPCHK(hipMallocAsync((void **)&ws, off, st));
     auto h2d = [&](size_t o, const void *src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpyAsync(ws + o, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
@@ -2872,12 +2880,7 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     // the specialised kernels run on side streams forked from the thread's
     // stream after the tables, so that small ones overlap; joined before
     // the reduction
-    const size_t n_spec = ents.size() - n_gen;
-    SideStreams *SS = nullptr;
-    const int n_side = (int)std::min<int64_t>(std::min<int64_t>(opts().batch_streams.load(), kSideStreams), (int64_t)n_spec);
     if (n_side > 1) {
-        rc = side_streams(D.id, SS);
-        if (rc) return rc;
         HIPCHK(hipEventRecord(SS->fork, st));
         for (int k = 0; k < n_side; ++k) HIPCHK(hipStreamWaitEvent(SS->s[k], SS->fork, 0));
     }
