@@ -1330,13 +1330,18 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // per item against 8.4 ms at 2048 (64 items per CU); the 40-arc grid in 16
 // parts 127 ms against 154 ms (one launch: 118 ms); items of 8 iterations
 // slowed the 30-arc graph's gradient sweep (2.3 against 1.9 ms at 32).
-int fill_item_log2(u64 iters, int cus, u64 parts)
+// min_log2: the smallest item for one launch where the sweep has that many
+// iterations (32 for the graph-specialised kernels and for gradients; the
+// generic forward kernel on small graphs is faster with items of one
+// chained block: on 256 graphs of 16 to 28 arcs, 20.9 ms in all at 8
+// iterations per item against 42.3 ms at 32)
+int fill_item_log2(u64 iters, int cus, u64 parts, int min_log2 = 5)
 {
     const u64 target = iters / ((u64)std::max(cus, 1) * 256ull * std::max<u64>(parts, 1));
     int c = 0;
     while (c < 12 && (2ull << c) <= target) ++c;
     if (parts <= 1)
-        while (c < 5 && (2ull << c) <= iters) ++c;
+        while (c < min_log2 && (2ull << c) <= iters) ++c;
     return c;
 }
 
@@ -1377,7 +1382,7 @@ int queue_sweep(const Request &rq, const Plan &P, const DeviceInfo &D, const Tun
     const u64 g_end = g_last | bmask;
     const u64 iters = g_end - g_base + 1;
 
-    const int clog_fill = fill_item_log2(iters, D.cus, rq.split_parts);
+    const int clog_fill = fill_item_log2(iters, D.cus, rq.split_parts, use_jit || rq.grad ? 5 : 0);
     int clog = tc.chunk_log2;
     // a size tuned for the whole counter would leave a short range's last
     // round of work items mostly idle
