@@ -2468,11 +2468,13 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
     constexpr double kTuneMargin = 0.01;
     auto measure = [&](const Cand &c, double &ns, bool grad = false) -> bool {
         ns = 1e300;
-        // the first pass warms the JIT cache; then the best of at least two
-        // timed passes, more for short samples (up to ~40 ms of timed
-        // kernel, at most 6 passes), whose times scatter more
+        // the best of at least two timed passes, more for short samples (up
+        // to ~40 ms of timed kernel, at most 6 passes), whose times scatter
+        // more; a pass whose kernel was compiled or loaded first is not
+        // timed (the kernels were compiled ahead, so that is one pass)
         double timed_ms = 0.0;
-        for (int rep = 0; rep < 7 && (rep < 3 || timed_ms < 40.0); ++rep) {
+        int timed = 0;
+        for (int rep = 0; rep < 8 && (timed < 2 || (timed < 6 && timed_ms < 40.0)); ++rep) {
             Request tmpl{};
             tmpl.force_chunk_log2 = c.clog;
             tmpl.force_check = c.check;
@@ -2490,9 +2492,10 @@ int bat_autotune(int32_t n, int32_t m, const bat_arc *arcs, const double *p, int
             u64 cnt = 0;
             bat_launch_info li;
             if (run_sync(n, m, arcs, p, s, t, 0, total, grad, res, cnt, &tmpl) || bat_last_launch(&li)) return false;
-            if (rep > 0) {
+            if (li.jit_ms == 0.0) {
                 ns = std::min(ns, li.kernel_ms * 1e6 / (double)li.vectors);
                 timed_ms += li.kernel_ms;
+                ++timed;
             }
         }
         return true;
