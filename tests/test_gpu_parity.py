@@ -968,6 +968,48 @@ def test_threads_share_device_and_reuse_resources():
         assert not errors, errors[:4]
 
 
+def test_threads_batched_specialised():
+    """Batched calls with graph-specialised kernels from several host
+    threads at once (each thread has its own stream and side streams; the
+    kernels are compiled once and shared), in two waves of threads: every
+    result equals the single-threaded one to the bit."""
+    import threading
+
+    B = _B()
+    batches = []
+    for k in range(3):
+        graphs, pblocks = _batch_inputs(1300 + k, 8, 6)
+        rng = np.random.default_rng(1400 + k)
+        for n, m in [(12, 20), (13, 22)]:
+            net = W.random_connected(n, m, seed=int(rng.integers(1 << 30)))
+            graphs.append((net.n, net.arcs, 0, n - 1))
+            pblocks.append(rng.uniform(0.3, 1.0, size=(6, m)))
+        batches.append((graphs, pblocks))
+    errors = []
+    with options(BAT_BATCH_JIT_ARCS=18):
+        want = [B.bat_reliability_batched(g, p) for g, p in batches]
+        assert B.bat_last_launch().specialised == 1
+
+        def worker(k):
+            try:
+                for j in range(6):
+                    i = (j + k) % len(batches)
+                    R, c = B.bat_reliability_batched(*batches[i])
+                    if not (np.array_equal(R, want[i][0]) and np.array_equal(c, want[i][1])):
+                        errors.append((k, i))
+            except Exception as e:  # noqa: BLE001 - reported below
+                errors.append((k, repr(e)))
+
+        for wave in range(2):
+            say("batched thread wave", wave)
+            ts = [threading.Thread(target=worker, args=(k,)) for k in range(3)]
+            for t in ts:
+                t.start()
+            for t in ts:
+                t.join()
+            assert not errors, errors[:4]
+
+
 def test_launch_info_names_the_kernel():
     """The launch description names the kernel that ran: the same launch
     twice reports the same identity, the generic and specialised kernels and
