@@ -968,6 +968,36 @@ def test_threads_share_device_and_reuse_resources():
         assert not errors, errors[:4]
 
 
+def test_batched_specialised_large_node_counts():
+    """Specialised batched kernels for graphs of more than 32 relevant nodes
+    (no kept block bottoms there): two cycles of 34 and 40 nodes, whose
+    reliability has a closed form, beside a small generic graph."""
+    B = _B()
+    rng = np.random.default_rng(1500)
+    graphs, pblocks, want = [], [], []
+    for n in (34, 40):
+        arcs = [(i, (i + 1) % n) for i in range(n)]
+        t = n // 2
+        pv = rng.uniform(0.9, 0.999, size=(3, n))
+        graphs.append((n, arcs, 0, t))
+        pblocks.append(pv)
+        want.append([1.0 - (1.0 - np.prod(p[:t])) * (1.0 - np.prod(p[t:])) for p in pv])
+    small = W.random_connected(6, 9, seed=5)
+    graphs.append((small.n, small.arcs, small.s, small.t))
+    pblocks.append(rng.uniform(0.3, 0.9, size=(3, small.m)))
+    with options(BAT_BATCH_JIT_ARCS=30):
+        R, c = B.bat_reliability_batched(graphs, pblocks)
+        assert B.bat_last_launch().specialised == 1
+    for g, n in enumerate((34, 40)):
+        t = n // 2
+        assert c[g] == (1 << n) - ((1 << t) - 1) * ((1 << (n - t)) - 1)
+        for j in range(3):
+            assert rel_ok(R[g, j], want[g][j], 1e-13), (n, j, R[g, j], want[g][j])
+    for j in range(3):
+        o = oracle.reliability(small.n, small.arcs, pblocks[2][j], small.s, small.t)
+        assert c[2] == o.count and rel_ok(R[2, j], o.sum)
+
+
 def test_threads_batched_specialised():
     """Batched calls with graph-specialised kernels from several host
     threads at once (each thread has its own stream and side streams; the
