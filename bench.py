@@ -38,7 +38,7 @@ if ROOT not in sys.path:
 CUS, CLOCK_HZ = 256, 2.4e9
 PEAK_LANE_OPS = CUS * 128 * CLOCK_HZ              # 7.86e13 int32 lane-ops/s
 PEAK_BIT_OPS = PEAK_LANE_OPS * 32                 # 2.52e15 bit-ops/s
-BOX_CPU_SHARE = 16                                # host cores one GPU's box grants a job
+HOST_CORES_PER_GPU = 16                           # host cores a one-GPU job is given
 
 # Hardware counters of the enumeration kernel on this workload
 # (profiles/bat_fwd_jit_grid5x5_m40.md), keyed by the launch they were
@@ -111,8 +111,8 @@ def copy_reference(gib: float):
 
 
 def host_cpu():
-    """CPU model and how many host processes the oracle legs use: the box's
-    share for one GPU (16), fewer if fewer cores are visible."""
+    """CPU model and how many host processes the oracle legs use: the host
+    cores a one-GPU job is given (16), fewer if fewer cores are visible."""
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -123,7 +123,7 @@ def host_cpu():
     except OSError:
         pass
     visible = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    procs = int(os.environ.get("BAT_BENCH_CPU_PROCS", "0")) or min(visible, BOX_CPU_SHARE)
+    procs = int(os.environ.get("BAT_BENCH_CPU_PROCS", "0")) or min(visible, HOST_CORES_PER_GPU)
     return model, visible, procs
 
 
@@ -147,7 +147,7 @@ def cpu_baselines(c2, c4, c3, sample_log2: int):
     algorithmic work per vector."""
     model, visible, procs = host_cpu()
     out = {"cpu_model": model, "cores_visible": visible, "cores_used": procs}
-    # headline: the 5x5 grid, forward, all the cores the box grants
+    # headline: the 5x5 grid, forward, all the host cores the job has
     r, k, chi = oracle_sample(c2, sample_log2, procs)
     out["c2"] = {
         "value": r.vectors / r.wall_s / 1e9, "unit": "Gvec/s", "cores": r.processes, "kind": "oracle",
@@ -480,7 +480,7 @@ def main():
                                                  "projected_time_to_R_s")}
         out["cpu_baseline"]["cpu_model"] = cpu["cpu_model"]
         out["cpu_baseline"]["cores_visible"] = cpu["cores_visible"]
-        out["cpu_baseline"]["cores_cap"] = "the host-core share of a one-GPU box (16)"
+        out["cpu_baseline"]["cores_cap"] = "the host cores a one-GPU job is given (16)"
         out["cpu_baseline_legs"] = {k: {kk: vv for kk, vv in cpu[k].items()
                                         if kk not in ("inspections_per_vector", "layers_per_vector",
                                                       "connected_fraction")}
