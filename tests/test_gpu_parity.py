@@ -998,6 +998,25 @@ def test_batched_specialised_large_node_counts():
         assert c[2] == o.count and rel_ok(R[2, j], o.sum)
 
 
+def test_batched_specialised_terminals_apart():
+    """A specialised batched kernel for a graph whose t no arc reaches (no
+    relaxation survives the plan): R = 0 and count 0 for every p-vector,
+    beside a connected graph checked against the frontier DP."""
+    B = _B()
+    apart = [(i, j) for i in range(7) for j in range(i + 1, 7)][:16]
+    net = W.random_connected(10, 18, seed=77)
+    rng = np.random.default_rng(1600)
+    graphs = [(9, apart, 0, 8), (net.n, net.arcs, net.s, net.t)]
+    pblocks = [rng.uniform(0.1, 1.0, size=(5, 16)), rng.uniform(0.1, 1.0, size=(5, net.m))]
+    with options(BAT_BATCH_JIT_ARCS=14):
+        R, c = B.bat_reliability_batched(graphs, pblocks)
+        assert B.bat_last_launch().specialised == 1
+    assert c[0] == 0 and np.all(R[0] == 0.0)
+    for j in range(5):
+        Rd, cd = frontier_dp.reliability(net.n, net.arcs, pblocks[1][j], net.s, net.t)
+        assert c[1] == cd and rel_ok(R[1, j], Rd)
+
+
 def test_threads_batched_specialised():
     """Batched calls with graph-specialised kernels from several host
     threads at once (each thread has its own stream and side streams; the
