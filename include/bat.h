@@ -502,6 +502,17 @@ int bat_valu_peak(double *lane_ops_per_s);
 int bat_jit_source(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, int32_t s, int32_t t, uint32_t flags,
                    int32_t grad, int32_t perm, char *buf, uint64_t *len);
 
+/*
+ * The source text of the graph-specialised multi-state kernel that
+ * bat_ms_reliability compiles for this graph, these states and capacities
+ * (capacity NULL: state k has capacity k) and demand 1 or 2 (BAT_EINVAL
+ * otherwise, or with no arcs).  Same conventions as bat_jit_source; the
+ * text does not depend on the probabilities.
+ */
+int bat_ms_jit_source(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const int32_t *n_states,
+                      const int32_t *capacity, int32_t s, int32_t t, int32_t demand, uint32_t flags, char *buf,
+                      uint64_t *len);
+
 #ifdef __cplusplus
 }
 #endif

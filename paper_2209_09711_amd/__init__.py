@@ -35,7 +35,8 @@ EXPORTED = ("bat_version", "bat_last_error", "bat_reliability", "bat_reliability
             "bat_reliability_grad_async", "bat_set_option", "bat_get_option", "bat_autotune",
             "bat_last_launch", "bat_jit_source", "bat_autotune_batched", "bat_reliability_ex",
             "bat_reliability_range_ex", "bat_reliability_checkpointed", "bat_valu_peak",
-            "bat_reliability_noalloc", "bat_ms_reliability", "bat_ms_reliability_range")
+            "bat_reliability_noalloc", "bat_ms_reliability", "bat_ms_reliability_range",
+            "bat_ms_jit_source")
 
 
 class bat_arc(ctypes.Structure):
@@ -90,6 +91,7 @@ def _load():
         "bat_autotune": ([i32, i32, P, P, i32, i32, P], ctypes.c_int),
         "bat_last_launch": ([P], ctypes.c_int),
         "bat_jit_source": ([i32, i32, P, i32, i32, ctypes.c_uint32, i32, i32, P, P], ctypes.c_int),
+        "bat_ms_jit_source": ([i32, i32, P, P, P, i32, i32, i32, ctypes.c_uint32, P, P], ctypes.c_int),
         "bat_autotune_batched": ([i32, P, P, P, P, P, i32, P, P], ctypes.c_int),
         "bat_reliability_ex": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, P, P, P, P, P], ctypes.c_int),
         "bat_reliability_range_ex": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, u64, u64, P, P, P, P, P],
@@ -390,6 +392,21 @@ def bat_jit_source(n_nodes: int, arcs, s: int, t: int, grad: bool = False, perm:
     _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, f, g, perm, None, ctypes.byref(n)))
     buf = ctypes.create_string_buffer(n.value)
     _check(_lib.bat_jit_source(n_nodes, a.shape[0], _ptr(a), s, t, f, g, perm, buf, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def bat_ms_jit_source(n_nodes: int, arcs, n_states, capacity, s: int, t: int, demand: int,
+                      directed: bool = False) -> str:
+    """The hiprtc source of the bit-sliced multi-state kernel that a whole
+    sweep with demand 1 or 2 compiles (diagnostics)."""
+    m = len(n_states)
+    w = [[1.0] * int(k) for k in n_states]
+    a, m, sg, cf, _ = _ms_args(arcs, n_states, capacity, w)
+    n = ctypes.c_uint64(0)
+    f = _flags(directed)
+    _check(_lib.bat_ms_jit_source(n_nodes, m, _ptr(a), _ptr(sg), _ptr(cf), s, t, demand, f, None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(_lib.bat_ms_jit_source(n_nodes, m, _ptr(a), _ptr(sg), _ptr(cf), s, t, demand, f, buf, ctypes.byref(n)))
     return buf.value.decode()
 
 

@@ -76,7 +76,7 @@ int fail(int code, const char *fmt, ...)
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
         window_test{1}, block_waves{-1}, super_restart{-1}, simd_waves{-1}, keep_bottom{-1}, series{1},
-        grad_keep_bottom{2}, ms_run{0}, jit_procs{16}, batch_jit_arcs{-1}, batch_streams{4}, jit_flush_req{0};
+        grad_keep_bottom{2}, ms_run{0}, jit_procs{16}, batch_jit_arcs{-1}, batch_streams{4}, ms_bits{1}, jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -102,6 +102,7 @@ struct Options {
         rd("BAT_JIT_PROCS", jit_procs);
         rd("BAT_BATCH_JIT_ARCS", batch_jit_arcs);
         rd("BAT_BATCH_STREAMS", batch_streams);
+        rd("BAT_MS_BITS", ms_bits);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -125,6 +126,7 @@ struct Options {
         if (!strcmp(k, "BAT_JIT_PROCS")) return &jit_procs;
         if (!strcmp(k, "BAT_BATCH_JIT_ARCS")) return &batch_jit_arcs;
         if (!strcmp(k, "BAT_BATCH_STREAMS")) return &batch_streams;
+        if (!strcmp(k, "BAT_MS_BITS")) return &ms_bits;
         if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
@@ -1965,9 +1967,175 @@ int ms_validate(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma,
     return BAT_OK;
 }
 
+// Whole sweeps with demand <= 2: the bit-sliced kernel (ms_bits_kernel in
+// bat_device.hpp) compiled for the graph and its states.  Slots in sweep
+// order: slot j joins su[j] and sv[j] and has sig[j] states whose
+// capacities and probabilities are capt / wt at off[j].
+int ms_bits_run(int32_t n, int32_t m, const int *su, const int *sv, const bat::u32 *sig, const bat::u32 *off,
+                const std::vector<int32_t> &capt, const std::vector<double> &wt, int32_t s, int32_t t, int32_t d,
+                bool directed, u64 N, double &R_hi, double &R_lo, u64 &count, std::string *src_only)
+{
+    // word slots: the longest prefix whose states fit the 32 bits of a word
+    int kw = 0;
+    u64 B = 1;
+    while (kw < m && B * sig[kw] <= 32) B *= sig[kw++];
+    const u64 n_out = N / B;
+    // run slots: as many as keep about 2^17 lane runs (8 wavefronts per CU)
+    // and a run within 2^31 steps (option BAT_MS_RUN > 0: runs of at most
+    // that many steps)
+    const u64 want_run = opts().ms_run.load() > 0 ? (u64)opts().ms_run.load() : std::max<u64>(1, n_out >> 17);
+    int kr = 0;
+    u64 run = 1;
+    while (kw + kr < m && run * sig[kw + kr] <= std::min<u64>(want_run, 1ull << 31)) run *= sig[kw + kr++];
+    const u64 n_lane = n_out / run;
+    const u64 n_items = (n_lane + bat::kWave - 1) / bat::kWave;
+    const u64 blocks = (n_items + bat::kWavesPerBlock - 1) / bat::kWavesPerBlock;
+    if (blocks > 0x7fffffffull) return fail(BAT_ETOOBIG, "too many work items (%llu)", (unsigned long long)n_items);
+    auto capof = [&](int j, u32 x) { return capt[off[j] + x]; };
+    // the kernel's constants
+    std::vector<u32> c1(m, 0u), ce1(m, 0u), ww1(m, 0u), wu1(m, 0u);
+    for (int j = 0; j < m; ++j)
+        for (u32 x = 0; x < sig[j]; ++x) {
+            if (capof(j, x) >= 1) c1[j] |= 1u << x;
+            if (capof(j, x) == 1) ce1[j] |= 1u << x;
+        }
+    u64 stride = 1;
+    for (int j = 0; j < kw; ++j) {
+        for (u64 b = 0; b < B; ++b) {
+            const u32 x = (u32)((b / stride) % sig[j]);
+            if (capof(j, x) >= 1) ww1[j] |= 1u << b;
+            if (capof(j, x) == 1) wu1[j] |= 1u << b;
+        }
+        stride *= sig[j];
+    }
+    const u32 full = B == 32 ? ~0u : (u32)((1ull << B) - 1ull);
+    std::string g = "\nstruct JitMs {\n";
+    auto num = [&](const char *k, u64 v) { g += std::string("  static constexpr unsigned ") + k + " = " + std::to_string(v) + "u;\n"; };
+    num("N", (u64)n);
+    num("S", (u64)s);
+    num("T", (u64)t);
+    num("M", (u64)m);
+    num("KW", (u64)kw);
+    num("KR", (u64)kr);
+    num("D", (u64)d);
+    num("FULL", full);
+    num("RUN", run);
+    g += std::string("  static constexpr bool DIR = ") + (directed ? "true" : "false") + ";\n";
+    auto arr = [&](const char *k, auto get) {
+        g += std::string("  static constexpr unsigned ") + k + "[" + std::to_string(m) + "] = {";
+        for (int j = 0; j < m; ++j) g += (j ? "," : "") + std::to_string((u64)get(j)) + "u";
+        g += "};\n";
+    };
+    arr("NU", [&](int j) { return su[j]; });
+    arr("NV", [&](int j) { return sv[j]; });
+    arr("SIG", [&](int j) { return sig[j]; });
+    arr("OFF", [&](int j) { return off[j]; });
+    arr("C1", [&](int j) { return c1[j]; });
+    arr("CE1", [&](int j) { return ce1[j]; });
+    arr("WW1", [&](int j) { return ww1[j]; });
+    arr("WU1", [&](int j) { return wu1[j]; });
+    g += "};\n";
+    g += "extern \"C\" __global__ void __launch_bounds__(256) bat_ms_bits(bat::MsBitsParams P) {\n"
+         "  __shared__ double tb[4][256];\n"
+         "  bat::ms_bits_kernel<JitMs>(P, tb);\n}\n";
+    if (src_only) {
+        *src_only = std::string(kDeviceSource) + g;
+        return BAT_OK;
+    }
+    DeviceInfo D;
+    int rc = current_device(D);
+    if (rc) return rc;
+    hipFunction_t fn;
+    double jit_ms = 0.0;
+    uint64_t kid = 0;
+    rc = jit_load(D, std::to_string(D.id) + " ms" + g, std::string(kDeviceSource) + g, "bat_ms_bits", fn, jit_ms, kid);
+    if (rc) return rc;
+    hipStream_t st;
+    rc = thread_stream(D.id, st);
+    if (rc) return rc;
+    // F tables of the word slots: Q_in(b) is the product of the word
+    // slots' probabilities in vector b, TB_h[x] the sum of Q_in(8h + i)
+    // over the bits i of x
+    std::vector<double> qin(32, 0.0), tb(1024, 0.0);
+    for (u64 b = 0; b < B; ++b) {
+        double q = 1.0;
+        u64 r = b;
+        for (int j = 0; j < kw; ++j) {
+            q *= wt[off[j] + (u32)(r % sig[j])];
+            r /= sig[j];
+        }
+        qin[b] = q;
+    }
+    for (int h = 0; h < 4; ++h)
+        for (int x = 0; x < 256; ++x) {
+            double a = 0.0;
+            for (int i = 0; i < 8; ++i)
+                if ((x >> i) & 1) a += qin[8 * h + i];
+            tb[256 * h + x] = a;
+        }
+    // workspace: input (tb | w) | partials | counts | output (res | count)
+    const size_t o_tb = 0;
+    const size_t o_w = align_up(o_tb + sizeof(double) * tb.size(), 256);
+    const size_t in_bytes = align_up(o_w + sizeof(double) * (wt.size() + 1), 256);
+    const u64 items = std::max<u64>(n_items, 1);
+    const size_t o_part = in_bytes;
+    const size_t o_pc = align_up(o_part + sizeof(double) * 2 * items, 256);
+    const size_t o_res = align_up(o_pc + sizeof(u64) * items, 256);
+    const size_t o_cnt = o_res + 2 * sizeof(double);
+    const size_t out_bytes = o_cnt + sizeof(u64) - o_res;
+    const size_t total = align_up(o_cnt + sizeof(u64) + 64, 256);
+    Scratch *S = nullptr;
+    const size_t out_host_off = in_bytes;
+    rc = scratch_reserve(D.id, st, total, out_host_off + out_bytes, S);
+    if (rc) return rc;
+    char *ws = S->dev;
+    memcpy(S->host + o_tb, tb.data(), sizeof(double) * tb.size());
+    memcpy(S->host + o_w, wt.data(), sizeof(double) * wt.size());
+    HIPCHK(hipMemcpyAsync(ws, S->host, in_bytes, hipMemcpyHostToDevice, st));
+    bat::MsBitsParams K;
+    memset(&K, 0, sizeof K);
+    K.n_lane = n_lane;
+    K.n_items = n_items;
+    K.tb = (const double *)(ws + o_tb);
+    K.w = (const double *)(ws + o_w);
+    K.part = (double *)(ws + o_part);
+    K.pcount = (u64 *)(ws + o_pc);
+    double *res = (double *)(ws + o_res);
+    u64 *cnt = (u64 *)(ws + o_cnt);
+    rc = events_ready();
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(t_state.ev[0], st));
+    HIPCHK(hipEventRecord(t_state.ev[1], st));
+    void *args[] = {&K};
+    if (blocks)
+        HIPCHK(hipModuleLaunchKernel(fn, (unsigned)blocks, 1, 1, (unsigned)(bat::kWave * bat::kWavesPerBlock), 1, 1, 0,
+                                     st, args, nullptr));
+    HIPCHK(hipEventRecord(t_state.ev[2], st));
+    HIPCHK(batk::reduce(st, (const double *)K.part, (const u64 *)K.pcount, n_items, 1, res, cnt));
+    HIPCHK(hipEventRecord(t_state.ev[3], st));
+    char *out = S->host + out_host_off;
+    HIPCHK(hipMemcpyAsync(out, ws + o_res, out_bytes, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bat_launch_info &I = t_state.info;
+    memset(&I, 0, sizeof I);
+    I.vectors = N;
+    I.n_chunks = (int32_t)std::min<u64>(n_items, 0x7fffffff);
+    I.chunk_log2 = -1;
+    I.relaxations = m;
+    I.specialised = 1;
+    I.jit_ms = jit_ms;
+    I.kernel_id = kid;
+    I.block_waves = bat::kWavesPerBlock;
+    t_state.have_launch = true;
+    memcpy(&R_hi, out, sizeof(double));
+    memcpy(&R_lo, out + sizeof(double), sizeof(double));
+    memcpy(&count, out + 2 * sizeof(double), sizeof(u64));
+    return BAT_OK;
+}
+
 int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, const int32_t *cap, const double *w,
            int32_t s, int32_t t, int32_t d, uint32_t flags, bool whole, u64 c_lo, u64 c_hi, double &R_hi,
-           double &R_lo, u64 &count)
+           double &R_lo, u64 &count, std::string *src_only = nullptr)
 {
     u64 N = 0;
     int32_t n_table = 0;
@@ -2043,6 +2211,17 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
         }
         o += (u32)sigma[i];
     }
+    // demand 1 or 2 over the whole space: the bit-sliced kernel
+    if (whole && d <= 2 && m > 0 && opts().ms_bits.load() != 0) {
+        std::vector<int> su(m), sv(m);
+        for (int j = 0; j < m; ++j) {
+            su[j] = K.u[j];
+            sv[j] = K.v[j];
+        }
+        return ms_bits_run(n, m, su.data(), sv.data(), K.sig, K.off, capt, wt, s, t, d, K.directed != 0, N, R_hi,
+                           R_lo, count, src_only);
+    }
+    if (src_only) return fail(BAT_EINVAL, "no bit-sliced kernel for this sweep (it needs demand 1 or 2 and arcs)");
     // slot 0's capacity nondecreasing in its state: the kernel's shortcuts
     // along slot 0 are exact
     K.warm = m > 0 ? 1u : 0u;
@@ -2433,6 +2612,32 @@ int bat_jit_source(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t
                  : jit_source(P, grad != 0,
                               jit_shape(grad != 0, (int)O.block_waves.load(), (int)O.super_restart.load(),
                                         (int)O.simd_waves.load(), (int)O.keep_bottom.load()));
+    const uint64_t need = (uint64_t)src.size() + 1;
+    const uint64_t have = *len;
+    *len = need;
+    if (!buf) return BAT_OK;
+    if (have < need) return fail(BAT_ETOOBIG, "buffer of %llu bytes, need %llu", (unsigned long long)have,
+                                 (unsigned long long)need);
+    memcpy(buf, src.c_str(), need);
+    return BAT_OK;
+}
+
+int bat_ms_jit_source(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *n_states, const int32_t *capacity,
+                      int32_t s, int32_t t, int32_t demand, uint32_t flags, char *buf, uint64_t *len)
+{
+    t_err.clear();
+    if (!len) return fail(BAT_EINVAL, "len is NULL");
+    if (m > 0 && !n_states) return fail(BAT_EINVAL, "NULL n_states");
+    // the source does not depend on the probabilities: any valid ones
+    int64_t pairs = 0;
+    for (int32_t i = 0; i < m; ++i) pairs += n_states[i] > 0 ? n_states[i] : 0;
+    if (pairs > batk::kMsMaxTable) return fail(BAT_ETOOBIG, "more than %d (arc, state) pairs", batk::kMsMaxTable);
+    std::vector<double> w((size_t)pairs + 1, 1.0);
+    std::string src;
+    double hi = 0.0, lo = 0.0;
+    u64 c = 0;
+    int rc = ms_run(n, m, arcs, n_states, capacity, w.data(), s, t, demand, flags, true, 0, 0, hi, lo, c, &src);
+    if (rc) return rc;
     const uint64_t need = (uint64_t)src.size() + 1;
     const uint64_t have = *len;
     *len = need;

@@ -212,3 +212,93 @@ def test_workload_full_size_sampled():
     # a lower demand can only be met more often
     R1, c1 = B.bat_ms_reliability(net.n, net.arcs, net.sigma, net.cap, net.w, net.s, net.t, 1)
     assert R1 >= R and c1 >= c
+
+
+def _random_states_net(seed, n, m, states):
+    rng = np.random.default_rng(seed)
+    arcs = [(i, i + 1) for i in range(n - 1)]
+    while len(arcs) < m:
+        u, v = (int(x) for x in rng.choice(n, 2, replace=False))
+        arcs.append((u, v))
+    sigma = [int(rng.choice(states)) for _ in range(m)]
+    cap = [[int(rng.integers(0, 3)) for _ in range(k)] for k in sigma]
+    w = [[float(x) for x in rng.dirichlet([1.0] * k)] for k in sigma]
+    return arcs, sigma, cap, w
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_bit_sliced_kernel_against_oracle_and_flow(seed):
+    """Whole sweeps with demand 1 or 2 run the bit-sliced kernel (the flow
+    reaches 1 when t is reachable over arcs of capacity >= 1, and 2 when
+    besides no single unit-capacity arc separates s and t): against the
+    oracle and against the augmenting-path kernel (option BAT_MS_BITS 0),
+    for 1-5 states with capacities 0-2 in any order, both arc readings,
+    default runs and runs of at most 3 and 9 uniform steps."""
+    B = _B()
+    n = 5 + seed % 4
+    states = [[2, 3], [1, 2, 3], [3], [2, 4, 5]][seed % 4]
+    m = {0: 12, 1: 12, 2: 10, 3: 8}[seed % 4]
+    arcs, sigma, cap, w = _random_states_net(700 + seed, n, m, states)
+    old_run, old_bits = B.bat_get_option("BAT_MS_RUN"), B.bat_get_option("BAT_MS_BITS")
+    try:
+        for directed in (False, True):
+            for d in (1, 2):
+                o = oracle.ms_reliability(n, arcs, sigma, cap, w, 0, n - 1, d, directed=directed)
+                B.bat_set_option("BAT_MS_BITS", 0)
+                B.bat_set_option("BAT_MS_RUN", 0)
+                Rf, cf = B.bat_ms_reliability(n, arcs, sigma, cap, w, 0, n - 1, d, directed=directed)
+                assert B.bat_last_launch().specialised == 0
+                assert cf == o.count and _ok(Rf, o.sum)
+                B.bat_set_option("BAT_MS_BITS", 1)
+                for run in (0, 3, 9):
+                    B.bat_set_option("BAT_MS_RUN", run)
+                    say("ms bits", seed, directed, d, run)
+                    R, c = B.bat_ms_reliability(n, arcs, sigma, cap, w, 0, n - 1, d, directed=directed)
+                    assert B.bat_last_launch().specialised == 1
+                    assert c == o.count and _ok(R, o.sum), (directed, d, run, R, o.sum, c, o.count)
+    finally:
+        B.bat_set_option("BAT_MS_RUN", old_run)
+        B.bat_set_option("BAT_MS_BITS", old_bits)
+
+
+@pytest.mark.parametrize("states", [2, 32])
+def test_bit_sliced_full_words(states):
+    """Words of exactly 32 vectors: five two-state arcs, or one arc of 32
+    states (capacities 0, 1, 2 repeating)."""
+    B = _B()
+    n = 6
+    arcs = [(0, 1), (1, 5), (0, 2), (2, 5), (1, 2), (0, 3), (3, 4), (4, 5), (3, 1)]
+    m = len(arcs)
+    rng = np.random.default_rng(states)
+    sigma = [states if i == 0 else 2 for i in range(m)]
+    cap = [[k % 3 for k in range(s_)] for s_ in sigma]
+    w = [[float(x) for x in rng.dirichlet([1.0] * s_)] for s_ in sigma]
+    for d in (1, 2):
+        say("ms bits full words", states, d)
+        R, c = B.bat_ms_reliability(n, arcs, sigma, cap, w, 0, n - 1, d)
+        assert B.bat_last_launch().specialised == 1
+        o = oracle.ms_reliability(n, arcs, sigma, cap, w, 0, n - 1, d)
+        assert c == o.count and _ok(R, o.sum), (d, R, o.sum)
+
+
+def test_bit_sliced_many_items_against_flow():
+    """A 3^16 space (many wavefronts, run slots chosen by the host): the
+    bit-sliced kernel against the augmenting-path kernel on the same graph,
+    demands 1 and 2, both arc readings."""
+    B = _B()
+    arcs, sigma, cap, w = _random_states_net(77, 10, 16, [3])
+    old = B.bat_get_option("BAT_MS_BITS")
+    try:
+        for directed in (False, True):
+            for d in (1, 2):
+                say("ms bits 3^16", directed, d)
+                B.bat_set_option("BAT_MS_BITS", 1)
+                R, c = B.bat_ms_reliability(10, arcs, sigma, cap, w, 0, 9, d, directed=directed)
+                assert B.bat_last_launch().specialised == 1
+                B.bat_set_option("BAT_MS_BITS", 0)
+                Rf, cf = B.bat_ms_reliability(10, arcs, sigma, cap, w, 0, 9, d, directed=directed)
+                assert c == cf and _ok(R, Rf), (directed, d, R, Rf)
+                if not directed:
+                    assert 0 < c < 3 ** 16
+    finally:
+        B.bat_set_option("BAT_MS_BITS", old)
