@@ -1980,10 +1980,12 @@ int ms_bits_run(int32_t n, int32_t m, const int *su, const int *sv, const bat::u
     u64 B = 1;
     while (kw < m && B * sig[kw] <= 32) B *= sig[kw++];
     const u64 n_out = N / B;
-    // run slots: as many as keep about 2^17 lane runs (8 wavefronts per CU)
-    // and a run within 2^31 steps (option BAT_MS_RUN > 0: runs of at most
-    // that many steps)
-    const u64 want_run = opts().ms_run.load() > 0 ? (u64)opts().ms_run.load() : std::max<u64>(1, n_out >> 17);
+    // run slots: as many as keep about 2^19 lane runs (32 wavefronts per
+    // CU: the kernel is latency-bound; on the 3^18 workload runs of 27
+    // steps took 0.94 ms, of 81 steps 1.15 ms, of 9 steps 1.09 ms) and a
+    // run within 2^31 steps (option BAT_MS_RUN > 0: runs of at most that
+    // many steps)
+    const u64 want_run = opts().ms_run.load() > 0 ? (u64)opts().ms_run.load() : std::max<u64>(1, n_out >> 19);
     int kr = 0;
     u64 run = 1;
     while (kw + kr < m && run * sig[kw + kr] <= std::min<u64>(want_run, 1ull << 31)) run *= sig[kw + kr++];

@@ -40,7 +40,8 @@ def _consts(src):
 
 def _closure(G, W, src, need, skip):
     """Reach from s over masks W without slot `skip`: sweeps until t holds
-    `need` or nothing changes (the kernel's loop, one lane)."""
+    `need` (tested after each sweep) or a sweep pair changes nothing (the
+    kernel's loop, one lane)."""
     r = [0] * G["N"]
     r[G["S"]] = src
     before = 0
@@ -53,8 +54,8 @@ def _closure(G, W, src, need, skip):
                 r[v] |= r[u] & W[j]
                 if not G["DIR"]:
                     r[u] |= r[v] & W[j]
-        if r[G["T"]] & need == need:
-            return r
+            if r[G["T"]] & need == need:
+                return r
         tot = sum(bin(x).count("1") for x in r)
         if tot == before:
             return r
