@@ -312,7 +312,14 @@ int bat_reliability_noalloc(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs
  * calling thread's stream; the same workspace rules as bat_reliability.
  *
  * bat_ms_reliability sweeps every vector (in any arc order it likes: R and
- * the count are sums).  bat_ms_reliability_range sweeps indices
+ * the count are sums).  With demand 1 or 2 it decides the flow test
+ * bit-sliced, up to 32 vectors per word, in a kernel compiled at run time
+ * for the graph, its states and capacities (hiprtc, cached like the other
+ * graph-specialised kernels; probabilities are run-time data): by
+ * max-flow min-cut the flow reaches 1 when t is reachable from s over the
+ * arcs of capacity >= 1, and 2 when besides no single arc of capacity
+ * exactly 1 separates s from t there.  Other demands, and ranges, run the
+ * augmenting-path kernel.  bat_ms_reliability_range sweeps indices
  * [c_lo, c_hi) in the order above and returns the partial sum as a
  * double-double (R_hi + R_lo) and its count.
  */
@@ -358,7 +365,12 @@ int bat_ms_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arc
  *                      order; R and counts never depend on it beyond
  *                      floating-point rounding
  *   "BAT_MS_RUN"       consecutive state vectors each lane of the
- *                      multi-state sweep decides (0 = automatic)
+ *                      multi-state augmenting-path sweep decides, and the
+ *                      most words each lane of the bit-sliced sweep
+ *                      (demand <= 2) steps through (0 = automatic)
+ *   "BAT_MS_BITS"      1 (default) = whole multi-state sweeps with demand 1
+ *                      or 2 run the bit-sliced kernel; 0 = always the
+ *                      augmenting-path kernel
  *   "BAT_WINDOW_TEST"  1 (default) = the graph-specialised sweeps (R, and
  *                      R with the gradient) test each window of 2048 iterations once, with all
  *                      11 word arcs up, and skips the chained blocks whose
