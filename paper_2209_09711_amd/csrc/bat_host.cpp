@@ -76,7 +76,7 @@ int fail(int code, const char *fmt, ...)
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
         window_test{1}, block_waves{-1}, super_restart{-1}, simd_waves{-1}, keep_bottom{-1}, series{1},
-        grad_keep_bottom{2}, ms_run{0}, jit_procs{16}, batch_jit_arcs{-1}, batch_streams{4}, ms_bits{1}, jit_flush_req{0};
+        grad_keep_bottom{2}, ms_run{0}, jit_procs{16}, batch_jit_arcs{-1}, batch_streams{4}, ms_bits{1}, batch_acc{1}, jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -103,6 +103,7 @@ struct Options {
         rd("BAT_BATCH_JIT_ARCS", batch_jit_arcs);
         rd("BAT_BATCH_STREAMS", batch_streams);
         rd("BAT_MS_BITS", ms_bits);
+        rd("BAT_BATCH_ACC", batch_acc);
     }
     std::atomic<int64_t> *find(const char *k)
     {
@@ -127,6 +128,7 @@ struct Options {
         if (!strcmp(k, "BAT_BATCH_JIT_ARCS")) return &batch_jit_arcs;
         if (!strcmp(k, "BAT_BATCH_STREAMS")) return &batch_streams;
         if (!strcmp(k, "BAT_MS_BITS")) return &ms_bits;
+        if (!strcmp(k, "BAT_BATCH_ACC")) return &batch_acc;
         if (!strcmp(k, "BAT_JIT_FLUSH")) return &jit_flush_req;
         return nullptr;
     }
@@ -922,6 +924,12 @@ JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int 
 // spills up to 16 p-vectors, beyond that 2 per SIMD (256 registers); at 3
 // per SIMD 32 accumulators spill inside the sweeps
 constexpr int batch_jit_waves(int np) { return np > 16 ? 8 : 12; }
+// the transposed accumulation (option BAT_BATCH_ACC 1, 17..32 p-vectors):
+// one accumulator per lane, blocks of kBatchTWaves wavefronts
+constexpr int kBatchTWaves = 16;
+static_assert(kBatchTWaves <= bat::kBatchTMaxWaves, "one LDS row per wavefront");
+bool batch_transposed(int np) { return np > 16 && np <= bat::kBatchCols && opts().batch_acc.load() == 1; }
+int batch_waves(int np) { return batch_transposed(np) ? kBatchTWaves : batch_jit_waves(np); }
 // p-vectors per specialised entry: 32 (blocks of 8 wavefronts) measured
 // faster than two entries of 16 (blocks of 12) on 256 graphs x 32
 // p-vectors, 18.7 against 19.4 ms: the closure then runs once
@@ -983,6 +991,11 @@ std::string jit_source(const Plan &P, bool grad, const JitShape &sh, int batch_n
              "bat_grad_jit(bat::KParams P) {\n"
              "  __shared__ bat::LdsTables L; __shared__ bat::LdsGrad LG;\n"
              "  bat::sweep_kernel<bat::StaticClosure<JitGraph>, true>(P, L, &LG);\n}\n";
+    else if (batch_np > 0 && batch_transposed(batch_np))
+        s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(bat::kWave * kBatchTWaves) +
+             ") bat_batch_jit(bat::KParams P) {\n"
+             "  __shared__ bat::LdsBatchT<" + std::to_string(batch_np) + "> L;\n"
+             "  bat::batch_kernel_t<bat::StaticClosure<JitGraph>, " + std::to_string(batch_np) + ">(P, L);\n}\n";
     else if (batch_np > 0)
         s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(bat::kWave * batch_jit_waves(batch_np)) +
              ") bat_batch_jit(bat::KParams P) {\n"
@@ -3017,7 +3030,8 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         auto t0 = std::chrono::steady_clock::now();
         std::vector<std::string> srcs(ents.size()), keys(ents.size()), todo;
         for (size_t i = n_gen; i < ents.size(); ++i) {
-            keys[i] = std::to_string(D.id) + " batch" + std::to_string(ents[i].P) + " " + plans[ents[i].graph].structure;
+            keys[i] = std::to_string(D.id) + " batch" + std::to_string(ents[i].P) +
+                      (batch_transposed((int)ents[i].P) ? "t " : " ") + plans[ents[i].graph].structure;
             srcs[i] = jit_source(plans[ents[i].graph], false, sh, (int)ents[i].P);
             std::lock_guard<std::mutex> lk(g_jit_mu);
             if (!g_jit.count(keys[i])) todo.push_back(srcs[i]);
@@ -3128,7 +3142,7 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         K.tables = (const double *)(ws + o_tab) + e.tab_off;
         K.part = (double *)(ws + o_part) + e.item_begin * batk::kBatchMaxP * 2;
         K.pcount = (u64 *)(ws + o_pc) + e.item_begin;
-        const u64 wpb = (u64)batch_jit_waves((int)e.P);
+        const u64 wpb = (u64)batch_waves((int)e.P);
         const u64 blocks = std::min<u64>((u64)D.cus, (e.n_items + wpb - 1) / wpb);
         void *args[] = {&K};
         hipStream_t ls = n_side > 1 ? SS->s[(i - n_gen) % (size_t)n_side] : st;
@@ -3139,7 +3153,7 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     // are queued: its persistent blocks then fill the CUs they leave
     if (n_gen_items > 0) {
         unsigned blocks = (unsigned)std::max<u64>(1, std::min<u64>((u64)D.cus, n_gen_items));
-        HIPCHK(batk::batched_sweep(st, blocks, nmax, BP));
+        HIPCHK(batk::batched_sweep(st, blocks, nmax, opts().batch_acc.load() == 1, BP));
     }
     for (int k = 0; n_side > 1 && k < n_side; ++k) {
         HIPCHK(hipEventRecord(SS->join[k], SS->s[k]));
@@ -3165,7 +3179,8 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         for (const Plan &pl : plans) nrel += pl.code.size();
         I.relaxations = (int32_t)nrel;
     }
-    I.kernel_id = aot_kernel_id("k_batched_dyn", (int)nmax, false) ^ spec_id;
+    I.kernel_id = aot_kernel_id(opts().batch_acc.load() == 1 ? "k_batched_dyn_t" : "k_batched_dyn", (int)nmax, false) ^
+                  spec_id;
     I.perm = -1;
     I.chain_log2 = (int32_t)bchain;
     I.check_every = 1;

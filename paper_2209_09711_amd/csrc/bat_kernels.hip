@@ -366,9 +366,164 @@ __global__ void __launch_bounds__(batk::batch_waves(NMAX) * bat::kWave) k_batche
     }
 }
 
+// The same queue with the transposed accumulation (bat_device.hpp,
+// AccumBatchT): lane (q, h) holds p-vector q's share of bytes h and h + 2
+// of every word; only the wavefront's mixed words (through an LDS row)
+// take byte-table reads, a word of ones adds Q_L(src) F_q(~0), and Q_L is
+// applied per word, so an item ends with one exchange between the lane
+// halves instead of a wavefront fold per p-vector.
+template <int NMAX>
+__global__ void __launch_bounds__(batk::batch_waves(NMAX) * bat::kWave) k_batched_dyn_t(batk::BatchParams B)
+{
+    using namespace batk;
+    constexpr int kBatchWaves = batch_waves(NMAX);
+    constexpr int kBatchThreads = kBatchWaves * bat::kWave;
+    constexpr int kSeg = 1 << kBatchSegLog;
+    __shared__ double tb[kBatchMaxP][bat::kBatchTStride];
+    __shared__ double a4[kBatchMaxP][4];
+    __shared__ double qlo[kBatchMaxP][kSeg + 1];
+    __shared__ double ql[kBatchMaxP][bat::kWave + 1];
+    __shared__ double qls[kBatchMaxP];
+    __shared__ u32 row[kBatchWaves][bat::kWave];
+    __shared__ double wsum[kBatchWaves][kBatchMaxP][2];
+    __shared__ u64 wcnt[kBatchWaves];
+    __shared__ u64 s_item;
+    __shared__ u32 s_entry;
+    const u32 tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+    const u32 qv = lane & 31u, half = lane >> 5;
+    const u32 sh0 = 8u * half, sh1 = sh0 + 16u;
+    for (;;) {
+        if (tid == 0) {
+            u64 it = atomicAdd(B.ctr, 1ull);
+            u32 lo = 0, hi = B.n_entries;   // entry e with item_start[e] <= it < item_start[e+1]
+            while (hi - lo > 1) {
+                u32 mid = (lo + hi) >> 1;
+                if (B.item_start[mid] <= it) lo = mid;
+                else hi = mid;
+            }
+            s_item = it;
+            s_entry = lo;
+        }
+        __syncthreads();
+        const u64 item = ((u64)__builtin_amdgcn_readfirstlane((u32)(s_item >> 32)) << 32) |
+                         __builtin_amdgcn_readfirstlane((u32)s_item);
+        if (item >= B.n_items) break;
+        const BatchEntry E = B.entries[__builtin_amdgcn_readfirstlane(s_entry)];
+        const u32 P = E.P, f = E.f;
+        const double *T = B.tables + E.tab_off;
+        for (u32 i = tid; i < P * 256u; i += kBatchThreads)
+            tb[i >> 8][i & 255u] = T[(u64)(i >> 8) * bat::kTablesFwd + bat::kTB + (i & 255u)];
+        for (u32 i = tid; i < P * 4u; i += kBatchThreads) a4[i >> 2][i & 3u] = T[(u64)(i >> 2) * bat::kTablesFwd + bat::kA4 + (i & 3u)];
+        for (u32 i = tid; i < P * (u32)kSeg; i += kBatchThreads)
+            qlo[i / kSeg][i % kSeg] = T[(u64)(i / kSeg) * bat::kTablesFwd + bat::kQlo + (i % kSeg)];
+        for (u32 i = tid; i < P * 64u; i += kBatchThreads)
+            ql[i >> 6][i & 63u] = T[(u64)(i >> 6) * bat::kTablesFwd + bat::kQL + (i & 63u)];
+        __syncthreads();
+        if (tid < P) {
+            double a = 0.0;
+            for (u32 k = 0; k < 64u; ++k) a += ql[tid][k];
+            qls[tid] = a;
+        }
+        __syncthreads();
+
+        // this lane's p-vector (lanes past P add nothing) and its bytes
+        const bool live = qv < P;
+        const u32 q = live ? qv : 0u;
+        const double a0 = live ? a4[q][half] : 0.0, a1 = live ? a4[q][half + 2u] : 0.0;
+        const double fullp = __builtin_fma(a1, tb[q][255], a0 * tb[q][255]);
+        const double qlsum = qls[q];
+        const u64 iters = 1ull << E.ubits;
+        const u64 seg = (item - E.item_begin) * kBatchWaves + w;
+        const u64 g0 = seg << f;
+        double tot = 0.0;
+        u64 cnt = 0;
+        if (g0 < iters) {
+            u64 g1 = g0 + (1ull << f) - 1ull;
+            if (g1 > iters - 1) g1 = iters - 1;
+            bat::KParams K;
+            K.s = E.s;
+            K.t = E.t;
+            K.n_relax = E.n_relax;
+            K.n_groups = E.n_groups;
+            K.prog = B.prog + E.prog_off;
+#pragma unroll
+            for (int b = 0; b < 6; ++b) K.ck_code[b] = E.ck_code[b];
+            K.check_every = B.check_every;
+            bat::DynClosure<NMAX> cl;
+            cl.init(lane, K);
+            const u64 chi = E.m >= 63 ? ~0ull : (1ull << E.m);
+            u32 *myrow = row[w];
+            auto add = [&](u64 g, u32 V) {
+                if (g == iters - 1) V &= bat::edge_mask(0ull, chi, g, lane);
+                cnt += __popc(V);
+                const u64 nz = __ballot(V != 0u);
+                if (nz == 0ull) return;
+                const u64 om = __ballot(V == ~0u);
+                const u64 mm = nz & ~om;
+                double x = 0.0;
+                if (om != 0ull) {
+                    double os = 0.0;
+                    if (om == ~0ull) {
+                        os = qlsum;
+                    } else {
+                        for (u64 b = om; b != 0ull; b &= b - 1ull) os += ql[q][__builtin_ctzll(b)];
+                    }
+                    x = os * fullp;
+                }
+                if (mm != 0ull) {
+                    // LDS operations of one wavefront complete in order
+                    myrow[lane] = V;
+                    asm volatile("" ::: "memory");
+                    for (u64 b = mm; b != 0ull; b &= b - 1ull) {
+                        const u32 sl = (u32)__builtin_ctzll(b);
+                        const u32 Vs = myrow[sl];
+                        const double t = __builtin_fma(a1, tb[q][(Vs >> sh1) & 255u], a0 * tb[q][(Vs >> sh0) & 255u]);
+                        x = __builtin_fma(ql[q][sl], t, x);
+                    }
+                    asm volatile("" ::: "memory");
+                }
+                const u32 glo = (u32)(g & ((1ull << f) - 1ull));
+                tot = __builtin_fma(qlo[q][glo], x, tot);
+            };
+            cl.sweep_range(g0, g1, E.chain, K, add, [](u64, u64) {});
+        }
+        // Q_hi of this segment, then the two halves of each p-vector
+        {
+            const double *Tq = T + (u64)q * bat::kTablesFwd;
+            double qhi = 1.0;
+            for (u32 b = f; b < E.ubits; ++b) qhi *= Tq[bat::kQG + 2 * b + (u32)((g0 >> b) & 1ull)];
+            tot *= qhi;
+            double h, l;
+            bat::two_sum(tot, bat::shfl_xor_d(tot, 32), h, l);
+            if (lane < P) {
+                wsum[w][lane][0] = h;
+                wsum[w][lane][1] = l;
+            }
+        }
+        u64 c = bat::wave_sum_u64(cnt);
+        if (lane == 0) wcnt[w] = c;
+        __syncthreads();
+        if (tid < P) {
+            double h = 0.0, l = 0.0;
+            for (int v = 0; v < kBatchWaves; ++v) bat::dd_add(h, l, wsum[v][tid][0], wsum[v][tid][1]);
+            B.part[(item * kBatchMaxP + tid) * 2] = h;
+            B.part[(item * kBatchMaxP + tid) * 2 + 1] = l;
+        }
+        if (tid == 0) {
+            u64 cs = 0;
+            for (int v = 0; v < kBatchWaves; ++v) cs += wcnt[v];
+            B.pcount[item] = cs;
+        }
+        __syncthreads();
+    }
+}
+
 template __global__ void k_batched_dyn<16>(batk::BatchParams);
 template __global__ void k_batched_dyn<32>(batk::BatchParams);
 template __global__ void k_batched_dyn<64>(batk::BatchParams);
+template __global__ void k_batched_dyn_t<16>(batk::BatchParams);
+template __global__ void k_batched_dyn_t<32>(batk::BatchParams);
+template __global__ void k_batched_dyn_t<64>(batk::BatchParams);
 
 // Entry e: thread q adds the entry's item partials of p-vector q in item
 // order; thread 0 of the entry holding p-vector 0 also adds the counts.
@@ -480,12 +635,18 @@ hipError_t batched_tables(hipStream_t st, const BatchEntry *entries, const u32 *
     return hipGetLastError();
 }
 
-hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, const BatchParams &B)
+hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, bool transposed, const BatchParams &B)
 {
     const dim3 g(blocks);
-    if (nmax <= 16) hipLaunchKernelGGL(k_batched_dyn<16>, g, dim3(batch_waves(16) * bat::kWave), 0, st, B);
-    else if (nmax <= 32) hipLaunchKernelGGL(k_batched_dyn<32>, g, dim3(batch_waves(32) * bat::kWave), 0, st, B);
-    else hipLaunchKernelGGL(k_batched_dyn<64>, g, dim3(batch_waves(64) * bat::kWave), 0, st, B);
+    if (transposed) {
+        if (nmax <= 16) hipLaunchKernelGGL(k_batched_dyn_t<16>, g, dim3(batch_waves(16) * bat::kWave), 0, st, B);
+        else if (nmax <= 32) hipLaunchKernelGGL(k_batched_dyn_t<32>, g, dim3(batch_waves(32) * bat::kWave), 0, st, B);
+        else hipLaunchKernelGGL(k_batched_dyn_t<64>, g, dim3(batch_waves(64) * bat::kWave), 0, st, B);
+    } else {
+        if (nmax <= 16) hipLaunchKernelGGL(k_batched_dyn<16>, g, dim3(batch_waves(16) * bat::kWave), 0, st, B);
+        else if (nmax <= 32) hipLaunchKernelGGL(k_batched_dyn<32>, g, dim3(batch_waves(32) * bat::kWave), 0, st, B);
+        else hipLaunchKernelGGL(k_batched_dyn<64>, g, dim3(batch_waves(64) * bat::kWave), 0, st, B);
+    }
     return hipGetLastError();
 }
 

@@ -48,7 +48,8 @@ struct BatchParams {
 hipError_t batched_tables(hipStream_t st, const BatchEntry *entries, const bat::u32 *pair_entry,
                           const bat::u32 *pair_pv, const bat::u64 *entry_p_off, const double *p, unsigned n_pairs,
                           double *tables);
-hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, const BatchParams &B);
+// transposed: the kernel with the transposed accumulation (k_batched_dyn_t)
+hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, bool transposed, const BatchParams &B);
 hipError_t batched_reduce(hipStream_t st, const BatchEntry *entries, unsigned n_entries, const double *part,
                           const bat::u64 *pcount, bat::u32 n_pvec, double *R, bat::u64 *counts);
 
