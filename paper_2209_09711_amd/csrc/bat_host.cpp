@@ -2992,6 +2992,10 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     while (n_gen < ents.size() && !specialised(ents[n_gen])) ++n_gen;
     nmax = 2;
     for (size_t i = 0; i < n_gen; ++i) nmax = std::max(nmax, (int)ents[i].n_nodes);
+    // wavefronts per block of the generic kernel: an item is that many
+    // segments
+    const bool gen_t = opts().batch_acc.load() == 1;
+    const int gen_waves = gen_t ? batk::batch_waves_t(nmax) : batk::batch_waves(nmax);
     u64 n_items = 0, n_gen_items = 0, tab = 0;
     std::vector<u64> item_start;
     std::vector<u32> pair_entry, pair_pv;
@@ -3002,7 +3006,7 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         u64 iters = 1ull << e.ubits;
         // a generic item is a block's worth of segments, a specialised one a
         // single segment (one wavefront)
-        u64 per_item = i < n_gen ? (u64)batk::batch_waves(nmax) << e.f : 1ull << e.f;
+        u64 per_item = i < n_gen ? (u64)gen_waves << e.f : 1ull << e.f;
         e.item_begin = n_items;
         e.n_items = (iters + per_item - 1) / per_item;
         e.tab_off = tab;
@@ -3153,7 +3157,7 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     // are queued: its persistent blocks then fill the CUs they leave
     if (n_gen_items > 0) {
         unsigned blocks = (unsigned)std::max<u64>(1, std::min<u64>((u64)D.cus, n_gen_items));
-        HIPCHK(batk::batched_sweep(st, blocks, nmax, opts().batch_acc.load() == 1, BP));
+        HIPCHK(batk::batched_sweep(st, blocks, nmax, gen_t, BP));
     }
     for (int k = 0; n_side > 1 && k < n_side; ++k) {
         HIPCHK(hipEventRecord(SS->join[k], SS->s[k]));
@@ -3179,13 +3183,13 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         for (const Plan &pl : plans) nrel += pl.code.size();
         I.relaxations = (int32_t)nrel;
     }
-    I.kernel_id = aot_kernel_id(opts().batch_acc.load() == 1 ? "k_batched_dyn_t" : "k_batched_dyn", (int)nmax, false) ^
+    I.kernel_id = aot_kernel_id(gen_t ? "k_batched_dyn_t" : "k_batched_dyn", (int)nmax, false) ^
                   spec_id;
     I.perm = -1;
     I.chain_log2 = (int32_t)bchain;
     I.check_every = 1;
     I.item_order = 0;
-    I.block_waves = (int32_t)batk::batch_waves(nmax);
+    I.block_waves = (int32_t)gen_waves;
     I.super_restart = 0;
     I.window_test = 0;
     t_state.have_launch = true;

@@ -373,10 +373,10 @@ __global__ void __launch_bounds__(batk::batch_waves(NMAX) * bat::kWave) k_batche
 // applied per word, so an item ends with one exchange between the lane
 // halves instead of a wavefront fold per p-vector.
 template <int NMAX>
-__global__ void __launch_bounds__(batk::batch_waves(NMAX) * bat::kWave) k_batched_dyn_t(batk::BatchParams B)
+__global__ void __launch_bounds__(batk::batch_waves_t(NMAX) * bat::kWave) k_batched_dyn_t(batk::BatchParams B)
 {
     using namespace batk;
-    constexpr int kBatchWaves = batch_waves(NMAX);
+    constexpr int kBatchWaves = batch_waves_t(NMAX);
     constexpr int kBatchThreads = kBatchWaves * bat::kWave;
     constexpr int kSeg = 1 << kBatchSegLog;
     __shared__ double tb[kBatchMaxP][bat::kBatchTStride];
@@ -639,9 +639,9 @@ hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, bool transpo
 {
     const dim3 g(blocks);
     if (transposed) {
-        if (nmax <= 16) hipLaunchKernelGGL(k_batched_dyn_t<16>, g, dim3(batch_waves(16) * bat::kWave), 0, st, B);
-        else if (nmax <= 32) hipLaunchKernelGGL(k_batched_dyn_t<32>, g, dim3(batch_waves(32) * bat::kWave), 0, st, B);
-        else hipLaunchKernelGGL(k_batched_dyn_t<64>, g, dim3(batch_waves(64) * bat::kWave), 0, st, B);
+        if (nmax <= 16) hipLaunchKernelGGL(k_batched_dyn_t<16>, g, dim3(batch_waves_t(16) * bat::kWave), 0, st, B);
+        else if (nmax <= 32) hipLaunchKernelGGL(k_batched_dyn_t<32>, g, dim3(batch_waves_t(32) * bat::kWave), 0, st, B);
+        else hipLaunchKernelGGL(k_batched_dyn_t<64>, g, dim3(batch_waves_t(64) * bat::kWave), 0, st, B);
     } else {
         if (nmax <= 16) hipLaunchKernelGGL(k_batched_dyn<16>, g, dim3(batch_waves(16) * bat::kWave), 0, st, B);
         else if (nmax <= 32) hipLaunchKernelGGL(k_batched_dyn<32>, g, dim3(batch_waves(32) * bat::kWave), 0, st, B);

@@ -12,6 +12,9 @@ namespace batk {
 // reach words, which persist across a chained block, fit beside the 32
 // accumulators in 168 VGPRs, else 2
 constexpr int batch_waves(int nmax) { return nmax <= 16 ? 12 : 8; }
+// the same for the transposed accumulation (k_batched_dyn_t: one
+// accumulator per lane, 118 VGPRs at 16 nodes, about 150 above)
+constexpr int batch_waves_t(int nmax) { return nmax <= 16 ? 16 : 12; }
 constexpr int kBatchWavesMax = 12;
 constexpr int kBatchMaxP = 32;                  // probability vectors per entry
 constexpr int kBatchSegLog = 6;                 // iterations per wavefront work unit: 2^f
