@@ -409,10 +409,18 @@ int bat_ms_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arc
  *                      side as for "BAT_JIT_PROCS"), the rest the generic
  *                      persistent kernel, in the same call; 0 = none,
  *                      -1 (default) = bat_autotune_batched's choice, else none
- *   "BAT_BATCH_STREAMS" side streams (1..4, default 4) the specialised
- *                      batched kernels are spread over, forked from and
+ *   "BAT_BATCH_STREAMS" side streams (1..4, default 3) the specialised
+ *                      batched kernels are spread over (each kernel to the
+ *                      least-loaded one, largest first), forked from and
  *                      joined to the calling thread's stream, so that
- *                      several run at once; 1 = the thread's stream only
+ *                      several run at once; 1 = the thread's stream only.
+ *                      With the thread's stream, 3 fill the 4 hardware
+ *                      queues HIP gives a process by default
+ *   "BAT_BATCH_ACC"    1 (default) = the batched kernels accumulate
+ *                      transposed (lane = one p-vector and two of the
+ *                      word's bytes; only mixed words read the byte
+ *                      tables); 0 = one accumulator per p-vector in every
+ *                      lane
  *   "BAT_JIT_PROCS"    how many graph-specialised kernels bat_autotune
  *                      compiles at once, each in a child process running
  *                      the helper program bat_jitc from the library's

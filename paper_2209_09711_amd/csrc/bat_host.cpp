@@ -76,7 +76,7 @@ int fail(int code, const char *fmt, ...)
 struct Options {
     std::atomic<int64_t> jit{2}, chunk_log2{0}, seg_log2{6}, check_every{1}, autotune{1}, perm{-1}, chain_log2{-1}, item_order{-1},
         window_test{1}, block_waves{-1}, super_restart{-1}, simd_waves{-1}, keep_bottom{-1}, series{1},
-        grad_keep_bottom{2}, ms_run{0}, jit_procs{16}, batch_jit_arcs{-1}, batch_streams{4}, ms_bits{1}, batch_acc{1}, jit_flush_req{0};
+        grad_keep_bottom{2}, ms_run{0}, jit_procs{16}, batch_jit_arcs{-1}, batch_streams{3}, ms_bits{1}, batch_acc{1}, jit_flush_req{0};
     Options()
     {
         auto rd = [](const char *k, std::atomic<int64_t> &v) {
@@ -3077,6 +3077,7 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         rc = side_streams(D.id, SS);
         if (rc) return rc;
     }
+    double side_load[kSideStreams] = {};
     HIPCHK(hipMallocAsync((void **)&ws, off, st));
     auto h2d = [&](size_t o, const void *src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpyAsync(ws + o, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
@@ -3149,7 +3150,12 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         const u64 wpb = (u64)batch_waves((int)e.P);
         const u64 blocks = std::min<u64>((u64)D.cus, (e.n_items + wpb - 1) / wpb);
         void *args[] = {&K};
-        hipStream_t ls = n_side > 1 ? SS->s[(i - n_gen) % (size_t)n_side] : st;
+        // the least-loaded side stream so far (entries come largest first)
+        int k_min = 0;
+        for (int k = 1; k < n_side; ++k)
+            if (side_load[k] < side_load[k_min]) k_min = k;
+        if (n_side > 0) side_load[k_min] += (double)e.P * (double)(1ull << e.m);
+        hipStream_t ls = n_side > 1 ? SS->s[k_min] : st;
         HIPCHK(hipModuleLaunchKernel(spec_fn[i], (unsigned)blocks, 1, 1, (unsigned)(bat::kWave * wpb), 1, 1, 0, ls, args,
                                      nullptr));
     }

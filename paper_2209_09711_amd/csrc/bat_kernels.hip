@@ -525,24 +525,42 @@ template __global__ void k_batched_dyn_t<16>(batk::BatchParams);
 template __global__ void k_batched_dyn_t<32>(batk::BatchParams);
 template __global__ void k_batched_dyn_t<64>(batk::BatchParams);
 
-// Entry e: thread q adds the entry's item partials of p-vector q in item
-// order; thread 0 of the entry holding p-vector 0 also adds the counts.
-extern "C" __global__ void __launch_bounds__(64)
+// Entry e: its items split into kReduceGroups consecutive runs; lane q of
+// group c adds p-vector q's partials of run c in item order, then thread q
+// adds the runs' sums in run order (a fixed order: the result does not
+// depend on timing).  The counts of the entry holding p-vector 0 likewise.
+constexpr int kReduceGroups = 8;
+extern "C" __global__ void __launch_bounds__(kReduceGroups * 32)
 k_batched_reduce(const batk::BatchEntry *__restrict__ entries, const double *__restrict__ part,
                  const u64 *__restrict__ pcount, u32 n_pvec, double *__restrict__ R, u64 *__restrict__ counts)
 {
+    __shared__ double hs[kReduceGroups][32][2];
+    __shared__ u64 cs[kReduceGroups];
     const batk::BatchEntry E = entries[blockIdx.x];
-    const u32 q = threadIdx.x;
-    if (q < E.P) {
-        double h = 0.0, l = 0.0;
-        for (u64 it = E.item_begin; it < E.item_begin + E.n_items; ++it)
+    const u32 q = threadIdx.x & 31u, c = threadIdx.x >> 5;
+    const u64 i0 = E.item_begin + E.n_items * c / kReduceGroups;
+    const u64 i1 = E.item_begin + E.n_items * (c + 1) / kReduceGroups;
+    double h = 0.0, l = 0.0;
+    if (q < E.P)
+        for (u64 it = i0; it < i1; ++it)
             bat::dd_add(h, l, part[(it * batk::kBatchMaxP + q) * 2], part[(it * batk::kBatchMaxP + q) * 2 + 1]);
-        R[(u64)E.graph * n_pvec + E.pv_base + q] = h + l;
+    hs[c][q][0] = h;
+    hs[c][q][1] = l;
+    if (q == 0) {
+        u64 n = 0;
+        for (u64 it = i0; it < i1; ++it) n += pcount[it];
+        cs[c] = n;
     }
-    if (q == 0 && E.pv_base == 0) {
-        u64 c = 0;
-        for (u64 it = E.item_begin; it < E.item_begin + E.n_items; ++it) c += pcount[it];
-        counts[E.graph] = c;
+    __syncthreads();
+    if (threadIdx.x < E.P) {
+        double th = 0.0, tl = 0.0;
+        for (int g = 0; g < kReduceGroups; ++g) bat::dd_add(th, tl, hs[g][threadIdx.x][0], hs[g][threadIdx.x][1]);
+        R[(u64)E.graph * n_pvec + E.pv_base + threadIdx.x] = th + tl;
+    }
+    if (threadIdx.x == 0 && E.pv_base == 0) {
+        u64 n = 0;
+        for (int g = 0; g < kReduceGroups; ++g) n += cs[g];
+        counts[E.graph] = n;
     }
 }
 
@@ -653,7 +671,7 @@ hipError_t batched_sweep(hipStream_t st, unsigned blocks, int nmax, bool transpo
 hipError_t batched_reduce(hipStream_t st, const BatchEntry *entries, unsigned n_entries, const double *part,
                           const u64 *pcount, u32 n_pvec, double *R, u64 *counts)
 {
-    hipLaunchKernelGGL(k_batched_reduce, dim3(n_entries), dim3(64), 0, st, entries, part, pcount, n_pvec, R, counts);
+    hipLaunchKernelGGL(k_batched_reduce, dim3(n_entries), dim3(kReduceGroups * 32), 0, st, entries, part, pcount, n_pvec, R, counts);
     return hipGetLastError();
 }
 
