@@ -222,10 +222,11 @@ int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes, const int3
  * graphs of at least m_max - 4, m_max - 2 or m_max arcs (m_max: the
  * batch's largest arc count; compile time is not counted), and caches the
  * fastest under the batch's structure (graphs, terminals, n_pvec; not p).
- * A specialised candidate must be 2% faster than the best generic one.
- * Later batched calls with that structure use the choice while
- * "BAT_AUTOTUNE" is 1 ("BAT_CHAIN_LOG2" and "BAT_BATCH_JIT_ARCS", when not
- * -1, override its parts).  *best_kernel_ms (may be NULL) receives the
+ * A specialised candidate must be 2% faster than the best generic one;
+ * with specialised kernels it then tries 2 and 1 side streams against 3
+ * (also a 2% win).  Later batched calls with that structure use the
+ * choice while "BAT_AUTOTUNE" is 1 ("BAT_CHAIN_LOG2", "BAT_BATCH_JIT_ARCS"
+ * and "BAT_BATCH_STREAMS", when not -1, override its parts).  *best_kernel_ms (may be NULL) receives the
  * best kernel time.
  * Results never depend on the choice beyond floating-point rounding.
  */
@@ -409,13 +410,15 @@ int bat_ms_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arc
  *                      side as for "BAT_JIT_PROCS"), the rest the generic
  *                      persistent kernel, in the same call; 0 = none,
  *                      -1 (default) = bat_autotune_batched's choice, else none
- *   "BAT_BATCH_STREAMS" side streams (1..4, default 3) the specialised
- *                      batched kernels are spread over (each kernel to the
+ *   "BAT_BATCH_STREAMS" side streams (1..4) the specialised batched
+ *                      kernels are spread over (each kernel to the
  *                      least-loaded one, largest first), forked from and
  *                      joined to the calling thread's stream, so that
- *                      several run at once; 1 = the thread's stream only.
- *                      With the thread's stream, 3 fill the 4 hardware
- *                      queues HIP gives a process by default
+ *                      several run at once; 0 = the thread's stream only;
+ *                      -1 (default) = bat_autotune_batched's choice of 1,
+ *                      2 or 3, else 3.  With the thread's stream, 3 fill
+ *                      the 4 hardware queues HIP gives a process by
+ *                      default when no other streams share them
  *   "BAT_BATCH_ACC"    1 (default) = the batched kernels accumulate
  *                      transposed (lane = one p-vector and two of the
  *                      word's bytes; only mixed words read the byte

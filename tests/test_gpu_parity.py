@@ -840,10 +840,12 @@ def test_batched_vs_plain_and_oracle(n_pvec):
 
 
 @pytest.mark.parametrize("n_pvec,jit_arcs,window,streams",
-                         [(1, 14, 1, 4), (7, 18, 1, 4), (32, 14, 1, 4), (45, 20, 1, 2), (9, 14, 0, 1)])
+                         [(1, 14, 1, 4), (7, 18, 1, 3), (32, 14, 1, 4), (45, 20, 1, 2), (9, 14, 0, 0),
+                          (20, 16, 1, 1)])
 def test_batched_specialised_kernels(n_pvec, jit_arcs, window, streams):
     """Graphs with at least jit_arcs arcs run graph-specialised batched
-    kernels (on up to `streams` side streams), the rest the generic launch,
+    kernels (on up to `streams` side streams, 0: the calling thread's
+    stream), the rest the generic launch,
     in the same call: counts equal to the generic launch's, R within
     rounding of it, and every p-vector index against the frontier DP (more
     than 32 p-vectors split into entries)."""
