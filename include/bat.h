@@ -313,13 +313,13 @@ int bat_reliability_noalloc(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs
  * calling thread's stream; the same workspace rules as bat_reliability.
  *
  * bat_ms_reliability sweeps every vector (in any arc order it likes: R and
- * the count are sums).  With demand 1 or 2 it decides the flow test
+ * the count are sums).  With demand 1 or 2 both entry points decide the flow test
  * bit-sliced, up to 32 vectors per word, in a kernel compiled at run time
  * for the graph, its states and capacities (hiprtc, cached like the other
  * graph-specialised kernels; probabilities are run-time data): by
  * max-flow min-cut the flow reaches 1 when t is reachable from s over the
  * arcs of capacity >= 1, and 2 when besides no single arc of capacity
- * exactly 1 separates s from t there.  Other demands, and ranges, run the
+ * exactly 1 separates s from t there.  Other demands run the
  * augmenting-path kernel.  bat_ms_reliability_range sweeps indices
  * [c_lo, c_hi) in the order above and returns the partial sum as a
  * double-double (R_hi + R_lo) and its count.
@@ -527,14 +527,16 @@ int bat_jit_source(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, int32_t
 
 /*
  * The source text of the graph-specialised multi-state kernel that
- * bat_ms_reliability compiles for this graph, these states and capacities
+ * bat_ms_reliability (c_lo = c_hi = 0) or bat_ms_reliability_range over
+ * [c_lo, c_hi) compiles for this graph, these states and capacities
  * (capacity NULL: state k has capacity k) and demand 1 or 2 (BAT_EINVAL
- * otherwise, or with no arcs).  Same conventions as bat_jit_source; the
- * text does not depend on the probabilities.
+ * otherwise, with no arcs, or for an empty or invalid range).  Same
+ * conventions as bat_jit_source; the text does not depend on the
+ * probabilities.
  */
 int bat_ms_jit_source(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, const int32_t *n_states,
-                      const int32_t *capacity, int32_t s, int32_t t, int32_t demand, uint32_t flags, char *buf,
-                      uint64_t *len);
+                      const int32_t *capacity, int32_t s, int32_t t, int32_t demand, uint32_t flags, uint64_t c_lo,
+                      uint64_t c_hi, char *buf, uint64_t *len);
 
 #ifdef __cplusplus
 }

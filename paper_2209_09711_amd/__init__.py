@@ -91,7 +91,7 @@ def _load():
         "bat_autotune": ([i32, i32, P, P, i32, i32, P], ctypes.c_int),
         "bat_last_launch": ([P], ctypes.c_int),
         "bat_jit_source": ([i32, i32, P, i32, i32, ctypes.c_uint32, i32, i32, P, P], ctypes.c_int),
-        "bat_ms_jit_source": ([i32, i32, P, P, P, i32, i32, i32, ctypes.c_uint32, P, P], ctypes.c_int),
+        "bat_ms_jit_source": ([i32, i32, P, P, P, i32, i32, i32, ctypes.c_uint32, u64, u64, P, P], ctypes.c_int),
         "bat_autotune_batched": ([i32, P, P, P, P, P, i32, P, P], ctypes.c_int),
         "bat_reliability_ex": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, P, P, P, P, P], ctypes.c_int),
         "bat_reliability_range_ex": ([i32, i32, P, P, i32, i32, ctypes.c_uint32, u64, u64, P, P, P, P, P],
@@ -396,17 +396,18 @@ def bat_jit_source(n_nodes: int, arcs, s: int, t: int, grad: bool = False, perm:
 
 
 def bat_ms_jit_source(n_nodes: int, arcs, n_states, capacity, s: int, t: int, demand: int,
-                      directed: bool = False) -> str:
-    """The hiprtc source of the bit-sliced multi-state kernel that a whole
-    sweep with demand 1 or 2 compiles (diagnostics)."""
-    m = len(n_states)
+                      directed: bool = False, c_lo: int = 0, c_hi: int = 0) -> str:
+    """The hiprtc source of the bit-sliced multi-state kernel that a sweep
+    with demand 1 or 2 compiles (diagnostics): the whole space when
+    c_lo = c_hi = 0, else the range [c_lo, c_hi)."""
     w = [[1.0] * int(k) for k in n_states]
     a, m, sg, cf, _ = _ms_args(arcs, n_states, capacity, w)
     n = ctypes.c_uint64(0)
     f = _flags(directed)
-    _check(_lib.bat_ms_jit_source(n_nodes, m, _ptr(a), _ptr(sg), _ptr(cf), s, t, demand, f, None, ctypes.byref(n)))
+    args = (n_nodes, m, _ptr(a), _ptr(sg), _ptr(cf), s, t, demand, f, int(c_lo), int(c_hi))
+    _check(_lib.bat_ms_jit_source(*args, None, ctypes.byref(n)))
     buf = ctypes.create_string_buffer(n.value)
-    _check(_lib.bat_ms_jit_source(n_nodes, m, _ptr(a), _ptr(sg), _ptr(cf), s, t, demand, f, buf, ctypes.byref(n)))
+    _check(_lib.bat_ms_jit_source(*args, buf, ctypes.byref(n)))
     return buf.value.decode()
 
 

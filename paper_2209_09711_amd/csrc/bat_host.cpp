@@ -1980,29 +1980,33 @@ int ms_validate(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma,
     return BAT_OK;
 }
 
-// Whole sweeps with demand <= 2: the bit-sliced kernel (ms_bits_kernel in
-// bat_device.hpp) compiled for the graph and its states.  Slots in sweep
-// order: slot j joins su[j] and sv[j] and has sig[j] states whose
-// capacities and probabilities are capt / wt at off[j].
+// Demand <= 2: the bit-sliced kernel (ms_bits_kernel in bat_device.hpp)
+// compiled for the graph and its states, over the vector indices
+// [c_lo, c_hi) (slot 0 least significant).  Slots in sweep order: slot j
+// joins su[j] and sv[j] and has sig[j] states whose capacities and
+// probabilities are capt / wt at off[j].
 int ms_bits_run(int32_t n, int32_t m, const int *su, const int *sv, const bat::u32 *sig, const bat::u32 *off,
                 const std::vector<int32_t> &capt, const std::vector<double> &wt, int32_t s, int32_t t, int32_t d,
-                bool directed, u64 N, double &R_hi, double &R_lo, u64 &count, std::string *src_only)
+                bool directed, u64 c_lo, u64 c_hi, double &R_hi, double &R_lo, u64 &count, std::string *src_only)
 {
     // word slots: the longest prefix whose states fit the 32 bits of a word
     int kw = 0;
     u64 B = 1;
     while (kw < m && B * sig[kw] <= 32) B *= sig[kw++];
-    const u64 n_out = N / B;
+    // the words the range touches
+    const u64 w_lo = c_lo / B, w_hi = c_hi > c_lo ? (c_hi + B - 1) / B : w_lo;
     // run slots: as many as keep about 2^19 lane runs (32 wavefronts per
     // CU: the kernel is latency-bound; on the 3^18 workload runs of 27
     // steps took 0.94 ms, of 81 steps 1.15 ms, of 9 steps 1.09 ms) and a
     // run within 2^31 steps (option BAT_MS_RUN > 0: runs of at most that
     // many steps)
-    const u64 want_run = opts().ms_run.load() > 0 ? (u64)opts().ms_run.load() : std::max<u64>(1, n_out >> 19);
+    const u64 want_run =
+        opts().ms_run.load() > 0 ? (u64)opts().ms_run.load() : std::max<u64>(1, (w_hi - w_lo) >> 19);
     int kr = 0;
     u64 run = 1;
     while (kw + kr < m && run * sig[kw + kr] <= std::min<u64>(want_run, 1ull << 31)) run *= sig[kw + kr++];
-    const u64 n_lane = n_out / run;
+    const u64 rl_lo = w_lo / run, rl_hi = (w_hi + run - 1) / run;
+    const u64 n_lane = rl_hi - rl_lo;
     const u64 n_items = (n_lane + bat::kWave - 1) / bat::kWave;
     const u64 blocks = (n_items + bat::kWavesPerBlock - 1) / bat::kWavesPerBlock;
     if (blocks > 0x7fffffffull) return fail(BAT_ETOOBIG, "too many work items (%llu)", (unsigned long long)n_items);
@@ -2033,6 +2037,7 @@ int ms_bits_run(int32_t n, int32_t m, const int *su, const int *sv, const bat::u
     num("KW", (u64)kw);
     num("KR", (u64)kr);
     num("D", (u64)d);
+    num("B", B);
     num("FULL", full);
     num("RUN", run);
     g += std::string("  static constexpr bool DIR = ") + (directed ? "true" : "false") + ";\n";
@@ -2110,6 +2115,9 @@ int ms_bits_run(int32_t n, int32_t m, const int *su, const int *sv, const bat::u
     bat::MsBitsParams K;
     memset(&K, 0, sizeof K);
     K.n_lane = n_lane;
+    K.rl_base = rl_lo;
+    K.c_lo = c_lo;
+    K.c_hi = c_hi;
     K.n_items = n_items;
     K.tb = (const double *)(ws + o_tb);
     K.w = (const double *)(ws + o_w);
@@ -2133,7 +2141,7 @@ int ms_bits_run(int32_t n, int32_t m, const int *su, const int *sv, const bat::u
     HIPCHK(hipStreamSynchronize(st));
     bat_launch_info &I = t_state.info;
     memset(&I, 0, sizeof I);
-    I.vectors = N;
+    I.vectors = c_hi - c_lo;
     I.n_chunks = (int32_t)std::min<u64>(n_items, 0x7fffffff);
     I.chunk_log2 = -1;
     I.relaxations = m;
@@ -2226,15 +2234,15 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
         }
         o += (u32)sigma[i];
     }
-    // demand 1 or 2 over the whole space: the bit-sliced kernel
-    if (whole && d <= 2 && m > 0 && opts().ms_bits.load() != 0) {
+    // demand 1 or 2: the bit-sliced kernel
+    if (d <= 2 && m > 0 && c_hi > c_lo && opts().ms_bits.load() != 0) {
         std::vector<int> su(m), sv(m);
         for (int j = 0; j < m; ++j) {
             su[j] = K.u[j];
             sv[j] = K.v[j];
         }
-        return ms_bits_run(n, m, su.data(), sv.data(), K.sig, K.off, capt, wt, s, t, d, K.directed != 0, N, R_hi,
-                           R_lo, count, src_only);
+        return ms_bits_run(n, m, su.data(), sv.data(), K.sig, K.off, capt, wt, s, t, d, K.directed != 0, c_lo, c_hi,
+                           R_hi, R_lo, count, src_only);
     }
     if (src_only) return fail(BAT_EINVAL, "no bit-sliced kernel for this sweep (it needs demand 1 or 2 and arcs)");
     // slot 0's capacity nondecreasing in its state: the kernel's shortcuts
@@ -2638,7 +2646,8 @@ int bat_jit_source(int32_t n, int32_t m, const bat_arc *arcs, int32_t s, int32_t
 }
 
 int bat_ms_jit_source(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *n_states, const int32_t *capacity,
-                      int32_t s, int32_t t, int32_t demand, uint32_t flags, char *buf, uint64_t *len)
+                      int32_t s, int32_t t, int32_t demand, uint32_t flags, uint64_t c_lo, uint64_t c_hi, char *buf,
+                      uint64_t *len)
 {
     t_err.clear();
     if (!len) return fail(BAT_EINVAL, "len is NULL");
@@ -2651,7 +2660,8 @@ int bat_ms_jit_source(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *
     std::string src;
     double hi = 0.0, lo = 0.0;
     u64 c = 0;
-    int rc = ms_run(n, m, arcs, n_states, capacity, w.data(), s, t, demand, flags, true, 0, 0, hi, lo, c, &src);
+    const bool whole = c_lo == 0 && c_hi == 0;
+    int rc = ms_run(n, m, arcs, n_states, capacity, w.data(), s, t, demand, flags, whole, c_lo, c_hi, hi, lo, c, &src);
     if (rc) return rc;
     const uint64_t need = (uint64_t)src.size() + 1;
     const uint64_t have = *len;

@@ -302,3 +302,36 @@ def test_bit_sliced_many_items_against_flow():
                     assert 0 < c < 3 ** 16
     finally:
         B.bat_set_option("BAT_MS_BITS", old)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_bit_sliced_ranges(seed):
+    """Index ranges with demand 1 or 2 run the bit-sliced kernel in the
+    caller's arc order, the words at both ends masked: ranges inside one
+    word, across a few words and long ones, against the oracle's range
+    sweep; adjacent ranges add up to the whole sweep."""
+    B = _B()
+    arcs, sigma, cap, w = _random_states_net(800 + seed, 7, 10, [2, 3])
+    N = int(np.prod(sigma))
+    rng = np.random.default_rng(seed)
+    lo = int(rng.integers(0, N // 2))
+    cases = [(lo, lo + 1), (lo, lo + 7), (lo, lo + 500), (0, N), (N // 3, N)]
+    old = B.bat_get_option("BAT_MS_RUN")
+    try:
+        for run in (0, 3):
+            B.bat_set_option("BAT_MS_RUN", run)
+            for directed in (False, True):
+                for d in (1, 2):
+                    say("ms bits ranges", seed, run, directed, d)
+                    for c_lo, c_hi in cases:
+                        r = B.bat_ms_reliability_range(7, arcs, sigma, cap, w, 0, 6, d, c_lo, c_hi, directed=directed)
+                        assert B.bat_last_launch().specialised == 1
+                        o = oracle.ms_reliability_range(7, arcs, sigma, cap, w, 0, 6, d, c_lo, c_hi, directed=directed)
+                        assert r.count == o.count and _ok(r.R, o.sum), (run, directed, d, c_lo, c_hi, r.R, o.sum)
+                    cut = int(rng.integers(1, N))
+                    a_ = B.bat_ms_reliability_range(7, arcs, sigma, cap, w, 0, 6, d, 0, cut, directed=directed)
+                    b_ = B.bat_ms_reliability_range(7, arcs, sigma, cap, w, 0, 6, d, cut, N, directed=directed)
+                    R, c = B.bat_ms_reliability(7, arcs, sigma, cap, w, 0, 6, d, directed=directed)
+                    assert a_.count + b_.count == c and _ok(a_.R + b_.R, R)
+    finally:
+        B.bat_set_option("BAT_MS_RUN", old)

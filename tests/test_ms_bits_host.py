@@ -62,15 +62,22 @@ def _closure(G, W, src, need, skip):
         before = tot
 
 
-def _replay(G):
-    """Count of the vectors the kernel's steps accept, over the whole space."""
-    M, KW, KR = G["M"], G["KW"], G["KR"]
-    n_lane = 1
-    for j in range(KW + KR, M):
-        n_lane *= G["SIG"][j]
+def _replay(G, c_lo=None, c_hi=None):
+    """Count of the vectors the kernel's steps accept, over the whole space
+    or the index range [c_lo, c_hi) (word slots least significant: vector
+    c is bit c mod B of word c div B, whose run step and lane run are the
+    quotient's low and high digits)."""
+    M, KW, KR, B, RUN = G["M"], G["KW"], G["KR"], G["B"], G["RUN"]
+    n_out = 1
+    for j in range(KW, M):
+        n_out *= G["SIG"][j]
+    if c_lo is None:
+        c_lo, c_hi = 0, n_out * B
+    rl_lo = (c_lo // B) // RUN
+    rl_hi = (-(-c_hi // B) + RUN - 1) // RUN
     mask = lambda bits, x: FULL32 if (bits >> x) & 1 else 0  # noqa: E731
     count = 0
-    for lane_run in range(n_lane):
+    for lane_run in range(rl_lo, rl_hi):
         W, U = [0] * M, [0] * M
         rl = lane_run
         for j in range(M):
@@ -81,10 +88,12 @@ def _replay(G):
                 rl //= G["SIG"][j]
                 W[j], U[j] = mask(G["C1"][j], x), mask(G["CE1"][j], x)
         xr = [0] * M
-        for _ in range(G["RUN"]):
+        for step in range(RUN):
             for j in range(KW, KW + KR):
                 W[j], U[j] = mask(G["C1"][j], xr[j]), mask(G["CE1"][j], xr[j])
-            r0 = _closure(G, W, G["FULL"], G["FULL"], -1)
+            c0 = (lane_run * RUN + step) * B
+            full = sum(1 << b for b in range(B) if c_lo <= c0 + b < c_hi) & G["FULL"]
+            r0 = _closure(G, W, full, full, -1)
             V = r0[G["T"]]
             if G["D"] == 2:
                 for j in range(M):
@@ -137,6 +146,35 @@ def test_bit_sliced_steps_count_like_the_oracle(seed, run):
                     assert rl == G["RUN"] <= run
                 o = oracle.ms_reliability(n, arcs, sigma, cap, w, 0, n - 1, d, directed=directed)
                 assert _replay(G) == o.count, (seed, run, directed, d)
+    finally:
+        B.bat_set_option("BAT_MS_RUN", old)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bit_sliced_ranges_count_like_the_oracle(seed):
+    """Index ranges (the caller's arc order, arc 0 most significant): the
+    kernel's steps over [c_lo, c_hi), the words at both ends masked, count
+    like the oracle's range sweep, for ranges inside one word, across a few
+    words, and from 0 to the end; runs of at most 1, 3 and 9 steps."""
+    B = _B()
+    n, arcs, sigma, cap = _random_net(40 + seed, 2, 3)
+    w = [[1.0 / k] * k for k in sigma]
+    N = int(np.prod(sigma))
+    rng = np.random.default_rng(seed)
+    lo = int(rng.integers(0, N // 2))
+    cases = [(lo, lo + 1), (lo, min(N, lo + 5)), (lo, min(N, lo + 200)), (0, N), (int(rng.integers(1, N)), N)]
+    old = B.bat_get_option("BAT_MS_RUN")
+    try:
+        for run in (1, 3, 9):
+            B.bat_set_option("BAT_MS_RUN", run)
+            for directed in (False, True):
+                for d in (1, 2):
+                    for c_lo, c_hi in cases:
+                        G = _consts(B.bat_ms_jit_source(n, arcs, sigma, cap, 0, n - 1, d, directed=directed,
+                                                        c_lo=c_lo, c_hi=c_hi))
+                        o = oracle.ms_reliability_range(n, arcs, sigma, cap, w, 0, n - 1, d, c_lo, c_hi,
+                                                        directed=directed)
+                        assert _replay(G, c_lo, c_hi) == o.count, (seed, run, directed, d, c_lo, c_hi)
     finally:
         B.bat_set_option("BAT_MS_RUN", old)
 
