@@ -23,14 +23,6 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-
-# HIP gives a process 4 hardware queues unless told otherwise.  Once torch's
-# default stream (the stream-ordered call below) and the library's stream
-# hold one each, the batched launch's side streams would share the other
-# two and its specialised kernels run two at a time instead of three
-# (12.8 ms instead of 10.7 ms on the batched workload).  Set before anything
-# starts the HIP runtime; an explicit setting in the environment wins.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

@@ -222,9 +222,9 @@ int bat_reliability_batched(int32_t n_graphs, const int32_t *n_nodes, const int3
  * graphs of at least m_max - 4, m_max - 2 or m_max arcs (m_max: the
  * batch's largest arc count; compile time is not counted), and caches the
  * fastest under the batch's structure (graphs, terminals, n_pvec; not p).
- * A specialised candidate must be 2% faster than the best generic one;
- * with specialised kernels it then tries 2 and 1 side streams against 3
- * (also a 2% win).  Later batched calls with that structure use the
+ * Each threshold is measured with 3, 2 and 1 side streams
+ * ("BAT_BATCH_STREAMS"); a specialised candidate must be 2% faster than
+ * the best generic one.  Later batched calls with that structure use the
  * choice while "BAT_AUTOTUNE" is 1 ("BAT_CHAIN_LOG2", "BAT_BATCH_JIT_ARCS"
  * and "BAT_BATCH_STREAMS", when not -1, override its parts).  *best_kernel_ms (may be NULL) receives the
  * best kernel time.

@@ -3084,9 +3084,9 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
     const size_t n_spec = ents.size() - n_gen;
     SideStreams *SS = nullptr;
     // how many side streams: forced by the option, else tuned, else 3 (with
-    // the thread's stream, the 4 hardware queues HIP gives a process; which
-    // queue a stream shares depends on the streams created before it, so
-    // the autotuner measures 1 to 3)
+    // the thread's stream, the 4 hardware queues HIP gives a process by
+    // default; which queue a stream shares depends on the streams the
+    // process made before it, so the autotuner measures 1 to 3)
     int want_side = bt.streams >= 0 ? bt.streams : 3;
     if (opts().batch_streams.load() >= 0 && (!force || bt.streams < 0)) want_side = (int)opts().batch_streams.load();
     const int n_side = (int)std::min<int64_t>(std::min<int64_t>(want_side, kSideStreams), (int64_t)n_spec);
@@ -3094,7 +3094,13 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         rc = side_streams(D.id, SS);
         if (rc) return rc;
     }
-    double side_load[kSideStreams] = {};
+    // lanes for the specialised kernels: the thread's stream (lane 0, which
+    // runs its share first and the generic persistent kernel after it) and
+    // the side streams; each kernel goes to the least-loaded lane, largest
+    // first, lane 0 starting with the generic kernel's work (weighted by
+    // its slower closure)
+    double lane_load[kSideStreams + 1] = {};
+    for (size_t i = 0; i < n_gen; ++i) lane_load[0] += 1.5 * (double)ents[i].P * (double)(1ull << ents[i].m);
     HIPCHK(hipMallocAsync((void **)&ws, off, st));
     auto h2d = [&](size_t o, const void *src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpyAsync(ws + o, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
@@ -3167,17 +3173,17 @@ int batched_impl(int32_t n_graphs, const int32_t *n_nodes, const int32_t *arc_of
         const u64 wpb = (u64)batch_waves((int)e.P);
         const u64 blocks = std::min<u64>((u64)D.cus, (e.n_items + wpb - 1) / wpb);
         void *args[] = {&K};
-        // the least-loaded side stream so far (entries come largest first)
         int k_min = 0;
-        for (int k = 1; k < n_side; ++k)
-            if (side_load[k] < side_load[k_min]) k_min = k;
-        if (n_side > 0) side_load[k_min] += (double)e.P * (double)(1ull << e.m);
-        hipStream_t ls = n_side > 0 ? SS->s[k_min] : st;
+        for (int k = 1; k <= n_side; ++k)
+            if (lane_load[k] < lane_load[k_min]) k_min = k;
+        lane_load[k_min] += (double)e.P * (double)(1ull << e.m);
+        hipStream_t ls = k_min > 0 ? SS->s[k_min - 1] : st;
         HIPCHK(hipModuleLaunchKernel(spec_fn[i], (unsigned)blocks, 1, 1, (unsigned)(bat::kWave * wpb), 1, 1, 0, ls, args,
                                      nullptr));
     }
     // the generic queue after the specialised kernels (the largest graphs)
-    // are queued: its persistent blocks then fill the CUs they leave
+    // are queued, behind lane 0's: its persistent blocks then fill the CUs
+    // the others leave
     if (n_gen_items > 0) {
         unsigned blocks = (unsigned)std::max<u64>(1, std::min<u64>((u64)D.cus, n_gen_items));
         HIPCHK(batk::batched_sweep(st, blocks, nmax, gen_t, BP));
@@ -3274,36 +3280,15 @@ extern "C" int bat_autotune_batched(int32_t n_graphs, const int32_t *n_nodes, co
         for (int32_t g = 0; g < n_graphs; ++g) m_max = std::max(m_max, arc_offsets[g + 1] - arc_offsets[g]);
         const double base = best;
         const BatchTune gen = bb;
+        // each threshold with 3, 2 and 1 side streams: which hardware queue
+        // a stream lands on depends on the streams the process made before
+        // it (torch's default stream, once used, holds one of HIP's 4), and
+        // a threshold measured on shared queues loses to a worse one
         for (int arcs_min : {m_max - 4, m_max - 2, m_max}) {
             if (arcs_min < bat::kWordBits + 3) continue;
-            BatchTune c = gen;
-            c.jit_arcs = arcs_min;
-            double ms = 1e300;
-            for (int rep = 0; rep < 3; ++rep) {
-                rc = batched_impl(n_graphs, n_nodes, arc_offsets, arcs, s, t, n_pvec, p, R.data(), cnt.data(), &c);
-                if (rc) return rc;
-                bat_launch_info li;
-                rc = bat_last_launch(&li);
-                if (rc) return rc;
-                if (rep > 0) ms = std::min(ms, li.kernel_ms);
-            }
-            if (verbose)
-                fprintf(stderr, "bat_autotune_batched: seg_log2=%d chain=%d specialised from %d arcs -> %.3f ms\n",
-                        c.seg, c.chain, arcs_min, ms);
-            if (ms < best && ms < base * 0.98) {
-                best = ms;
-                bb = c;
-            }
-        }
-        if (bb.jit_arcs < 0) bb.jit_arcs = 0;  // tuned: none
-        // side streams of the specialised kernels: which hardware queue a
-        // stream lands on depends on the streams the process made before,
-        // so measure 1 and 2 against the default 3 (a 2% win)
-        if (bb.jit_arcs > 0) {
-            const double base3 = best;
-            const BatchTune sp = bb;
-            for (int ns : {2, 1}) {
-                BatchTune c = sp;
+            for (int ns : {3, 2, 1}) {
+                BatchTune c = gen;
+                c.jit_arcs = arcs_min;
                 c.streams = ns;
                 double ms = 1e300;
                 for (int rep = 0; rep < 3; ++rep) {
@@ -3315,14 +3300,17 @@ extern "C" int bat_autotune_batched(int32_t n_graphs, const int32_t *n_nodes, co
                     if (rep > 0) ms = std::min(ms, li.kernel_ms);
                 }
                 if (verbose)
-                    fprintf(stderr, "bat_autotune_batched: specialised from %d arcs on %d side streams -> %.3f ms\n",
-                            c.jit_arcs, ns, ms);
-                if (ms < best && ms < base3 * 0.98) {
+                    fprintf(stderr,
+                            "bat_autotune_batched: seg_log2=%d chain=%d specialised from %d arcs on %d side streams "
+                            "-> %.3f ms\n",
+                            c.seg, c.chain, arcs_min, ns, ms);
+                if (ms < best && ms < base * 0.98) {
                     best = ms;
                     bb = c;
                 }
             }
         }
+        if (bb.jit_arcs < 0) bb.jit_arcs = 0;  // tuned: none
     }
     {
         std::lock_guard<std::mutex> lk(g_btune_mu);
