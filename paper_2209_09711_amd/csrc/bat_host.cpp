@@ -924,11 +924,12 @@ JitShape jit_shape(bool grad, int waves, int super_restart, int simd_waves, int 
 // spills up to 16 p-vectors, beyond that 2 per SIMD (256 registers); at 3
 // per SIMD 32 accumulators spill inside the sweeps
 constexpr int batch_jit_waves(int np) { return np > 16 ? 8 : 12; }
-// the transposed accumulation (option BAT_BATCH_ACC 1, 17..32 p-vectors):
-// one accumulator per lane, blocks of kBatchTWaves wavefronts
+// the transposed accumulation (option BAT_BATCH_ACC 1, 9..32 p-vectors:
+// two lanes per p-vector above 16, else four): one accumulator per lane,
+// blocks of kBatchTWaves wavefronts
 constexpr int kBatchTWaves = 16;
 static_assert(kBatchTWaves <= bat::kBatchTMaxWaves, "one LDS row per wavefront");
-bool batch_transposed(int np) { return np > 16 && np <= bat::kBatchCols && opts().batch_acc.load() == 1; }
+bool batch_transposed(int np) { return np > 8 && np <= bat::kBatchCols && opts().batch_acc.load() == 1; }
 int batch_waves(int np) { return batch_transposed(np) ? kBatchTWaves : batch_jit_waves(np); }
 // p-vectors per specialised entry: 32 (blocks of 8 wavefronts) measured
 // faster than two entries of 16 (blocks of 12) on 256 graphs x 32

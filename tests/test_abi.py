@@ -163,13 +163,13 @@ def test_jit_sources_compile(tmp_path, grad):
 
 
 @pytest.mark.skipif(_hipcc() is None, reason="hipcc not installed")
-@pytest.mark.parametrize("npv,acc", [(1, 1), (16, 1), (17, 1), (32, 1), (32, 0)])
+@pytest.mark.parametrize("npv,acc", [(1, 1), (8, 1), (9, 1), (16, 1), (16, 0), (17, 1), (32, 1), (32, 0)])
 def test_batch_jit_sources_compile(tmp_path, npv, acc):
     """The graph-specialised batched sweep compiles for gfx950 for 1 to 32
-    p-vectors: above 16 with the transposed accumulation (one accumulator
+    p-vectors: above 8 with the transposed accumulation (one accumulator
     per lane) in blocks of 16 wavefronts, or (option BAT_BATCH_ACC 0) with
-    32 per-lane accumulators in blocks of 8; up to 16 per-lane accumulators
-    in blocks of 12; no scratch access inside the sweep loops."""
+    per-lane accumulators, 32 in blocks of 8 and up to 16 in blocks of 12;
+    no scratch access inside the sweep loops."""
     import subprocess
     import bat_workloads as W
     import paper_2209_09711_amd as B
@@ -181,7 +181,7 @@ def test_batch_jit_sources_compile(tmp_path, npv, acc):
         src = B.bat_jit_source(net.n, net.arcs, net.s, net.t, batch_pvec=npv)
     finally:
         B.bat_set_option("BAT_BATCH_ACC", old)
-    transposed = acc == 1 and npv > 16
+    transposed = acc == 1 and npv > 8
     assert "bat_batch_jit" in src and (f"LdsBatchT<{npv}>" if transposed else f"LdsBatch<{npv}>") in src
     waves = 16 if transposed else (8 if npv > 16 else 12)
     assert f"__launch_bounds__({64 * waves})" in src
