@@ -368,7 +368,8 @@ __global__ void __launch_bounds__(batk::batch_waves(NMAX) * bat::kWave) k_batche
 
 // The same queue with the transposed accumulation (bat_device.hpp,
 // AccumBatchT): lane (q, h) holds p-vector q's share of bytes h and h + 2
-// of every word; only the wavefront's mixed words (through an LDS row)
+// of every word (of byte h alone, four lanes per p-vector, for items of
+// up to 16 p-vectors); only the wavefront's mixed words (through an LDS row)
 // take byte-table reads, a word of ones adds Q_L(src) F_q(~0), and Q_L is
 // applied per word, so an item ends with one exchange between the lane
 // halves instead of a wavefront fold per p-vector.
@@ -390,8 +391,6 @@ __global__ void __launch_bounds__(batk::batch_waves_t(NMAX) * bat::kWave) k_batc
     __shared__ u64 s_item;
     __shared__ u32 s_entry;
     const u32 tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
-    const u32 qv = lane & 31u, half = lane >> 5;
-    const u32 sh0 = 8u * half, sh1 = sh0 + 16u;
     for (;;) {
         if (tid == 0) {
             u64 it = atomicAdd(B.ctr, 1ull);
@@ -426,10 +425,16 @@ __global__ void __launch_bounds__(batk::batch_waves_t(NMAX) * bat::kWave) k_batc
         }
         __syncthreads();
 
-        // this lane's p-vector (lanes past P add nothing) and its bytes
+        // this lane's p-vector (lanes past P add nothing) and its bytes:
+        // above 16 p-vectors two lanes of two bytes each per p-vector,
+        // else four lanes of one byte (uniform: P is the item's)
+        const bool two = P > 16u;
+        const u32 qn = two ? 32u : 16u;
+        const u32 qv = lane & (qn - 1u), half = lane / qn;
+        const u32 sh0 = 8u * half, sh1 = sh0 + 16u;
         const bool live = qv < P;
         const u32 q = live ? qv : 0u;
-        const double a0 = live ? a4[q][half] : 0.0, a1 = live ? a4[q][half + 2u] : 0.0;
+        const double a0 = live ? a4[q][half] : 0.0, a1 = (live && two) ? a4[q][(half + 2u) & 3u] : 0.0;
         const double fullp = __builtin_fma(a1, tb[q][255], a0 * tb[q][255]);
         const double qlsum = qls[q];
         const u64 iters = 1ull << E.ubits;
@@ -477,7 +482,8 @@ __global__ void __launch_bounds__(batk::batch_waves_t(NMAX) * bat::kWave) k_batc
                     for (u64 b = mm; b != 0ull; b &= b - 1ull) {
                         const u32 sl = (u32)__builtin_ctzll(b);
                         const u32 Vs = myrow[sl];
-                        const double t = __builtin_fma(a1, tb[q][(Vs >> sh1) & 255u], a0 * tb[q][(Vs >> sh0) & 255u]);
+                        double t = a0 * tb[q][(Vs >> sh0) & 255u];
+                        if (two) t = __builtin_fma(a1, tb[q][(Vs >> sh1) & 255u], t);
                         x = __builtin_fma(ql[q][sl], t, x);
                     }
                     asm volatile("" ::: "memory");
@@ -495,6 +501,10 @@ __global__ void __launch_bounds__(batk::batch_waves_t(NMAX) * bat::kWave) k_batc
             tot *= qhi;
             double h, l;
             bat::two_sum(tot, bat::shfl_xor_d(tot, 32), h, l);
+            if (!two) {
+                const double oh = bat::shfl_xor_d(h, 16), ol = bat::shfl_xor_d(l, 16);
+                bat::dd_add(h, l, oh, ol);
+            }
             if (lane < P) {
                 wsum[w][lane][0] = h;
                 wsum[w][lane][1] = l;
