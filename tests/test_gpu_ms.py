@@ -335,3 +335,28 @@ def test_bit_sliced_ranges(seed):
                     assert a_.count + b_.count == c and _ok(a_.R + b_.R, R)
     finally:
         B.bat_set_option("BAT_MS_RUN", old)
+
+
+def test_bit_sliced_range_in_a_huge_space():
+    """Short ranges inside and at the top of a 3^32-vector space (32
+    three-level arcs, 1.85e15 vectors: large lane-run and word indices),
+    demands 1 and 2, against the oracle's range sweep."""
+    B = _B()
+    n = 12
+    rng = np.random.default_rng(32)
+    arcs = [(i, i + 1) for i in range(n - 1)]
+    while len(arcs) < 32:
+        u, v = (int(x) for x in rng.choice(n, 2, replace=False))
+        arcs.append((u, v))
+    sigma = [3] * 32
+    cap = [[0, 1, 2]] * 32
+    w = [[float(x) for x in rng.dirichlet([1.0, 1.0, 1.0])] for _ in range(32)]
+    N = 3 ** 32
+    for d in (1, 2):
+        for c_lo in (int(N * 0.37) + 12345, int(N * 0.83) + 12345, N - 40004):
+            c_hi = c_lo + 40003
+            say("ms bits huge space", d, c_lo, c_hi)
+            r = B.bat_ms_reliability_range(n, arcs, sigma, cap, w, 0, n - 1, d, c_lo, c_hi)
+            assert B.bat_last_launch().specialised == 1
+            o = oracle.ms_reliability_range(n, arcs, sigma, cap, w, 0, n - 1, d, c_lo, c_hi)
+            assert r.count == o.count and _ok(r.R, o.sum), (d, c_lo, c_hi, r.R, o.sum)
