@@ -478,11 +478,19 @@ def main():
             Rm, cm = B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, msn.d)
             mw = time.perf_counter() - t0
             mks.append(B.bat_last_launch().kernel_ms)
+        bits = bool(B.bat_last_launch().specialised)
+        # the same sweep on the augmenting-path kernel, for comparison
+        old_bits = B.bat_get_option("BAT_MS_BITS")
+        B.bat_set_option("BAT_MS_BITS", 0)
+        Rf, cf = B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, msn.d)
+        fk = B.bat_last_launch().kernel_ms
+        B.bat_set_option("BAT_MS_BITS", old_bits)
+        assert cf == cm
         ms_out = {"workload": f"random n={msn.n} m={msn.m} (seed 220909711/5), 3 capacity levels per arc, "
                               f"demand {msn.d}, {msn.space} state vectors",
                   "R": Rm, "count": cm, "kernel_ms": min(mks), "wall_ms": mw * 1e3,
                   "value": msn.space / (min(mks) / 1e3) / 1e9, "unit": "Gvec/s",
-                  "bit_sliced": bool(B.bat_last_launch().specialised)}
+                  "bit_sliced": bits, "flow_kernel_ms": fk, "flow_R_rel_diff": abs(Rf - Rm) / Rm if Rm else 0.0}
         out["multistate"] = ms_out
 
     cpu = None
