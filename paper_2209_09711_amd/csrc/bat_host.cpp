@@ -1981,7 +1981,7 @@ int ms_validate(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma,
     return BAT_OK;
 }
 
-// Demand <= 2: the bit-sliced kernel (ms_bits_kernel in bat_device.hpp)
+// Demand <= 3: the bit-sliced kernel (ms_bits_kernel in bat_device.hpp)
 // compiled for the graph and its states, over the vector indices
 // [c_lo, c_hi) (slot 0 least significant).  Slots in sweep order: slot j
 // joins su[j] and sv[j] and has sig[j] states whose capacities and
@@ -2013,18 +2013,23 @@ int ms_bits_run(int32_t n, int32_t m, const int *su, const int *sv, const bat::u
     if (blocks > 0x7fffffffull) return fail(BAT_ETOOBIG, "too many work items (%llu)", (unsigned long long)n_items);
     auto capof = [&](int j, u32 x) { return capt[off[j] + x]; };
     // the kernel's constants
-    std::vector<u32> c1(m, 0u), ce1(m, 0u), ww1(m, 0u), wu1(m, 0u);
+    std::vector<u32> c1(m, 0u), ce1(m, 0u), ce12(m, 0u), ww1(m, 0u), wu1(m, 0u), wu12(m, 0u);
+    u32 upair = 0u;
     for (int j = 0; j < m; ++j)
         for (u32 x = 0; x < sig[j]; ++x) {
             if (capof(j, x) >= 1) c1[j] |= 1u << x;
             if (capof(j, x) == 1) ce1[j] |= 1u << x;
+            if (capof(j, x) == 1 || capof(j, x) == 2) ce12[j] |= 1u << x;
         }
+    for (int j = 0; j < m; ++j)
+        if (ce1[j]) upair |= 1u << j;
     u64 stride = 1;
     for (int j = 0; j < kw; ++j) {
         for (u64 b = 0; b < B; ++b) {
             const u32 x = (u32)((b / stride) % sig[j]);
             if (capof(j, x) >= 1) ww1[j] |= 1u << b;
             if (capof(j, x) == 1) wu1[j] |= 1u << b;
+            if (capof(j, x) == 1 || capof(j, x) == 2) wu12[j] |= 1u << b;
         }
         stride *= sig[j];
     }
@@ -2041,6 +2046,7 @@ int ms_bits_run(int32_t n, int32_t m, const int *su, const int *sv, const bat::u
     num("B", B);
     num("FULL", full);
     num("RUN", run);
+    num("UPAIR", upair);
     g += std::string("  static constexpr bool DIR = ") + (directed ? "true" : "false") + ";\n";
     auto arr = [&](const char *k, auto get) {
         g += std::string("  static constexpr unsigned ") + k + "[" + std::to_string(m) + "] = {";
@@ -2053,8 +2059,10 @@ int ms_bits_run(int32_t n, int32_t m, const int *su, const int *sv, const bat::u
     arr("OFF", [&](int j) { return off[j]; });
     arr("C1", [&](int j) { return c1[j]; });
     arr("CE1", [&](int j) { return ce1[j]; });
+    arr("CE12", [&](int j) { return ce12[j]; });
     arr("WW1", [&](int j) { return ww1[j]; });
     arr("WU1", [&](int j) { return wu1[j]; });
+    arr("WU12", [&](int j) { return wu12[j]; });
     g += "};\n";
     g += "extern \"C\" __global__ void __launch_bounds__(256) bat_ms_bits(bat::MsBitsParams P) {\n"
          "  __shared__ double tb[4][256];\n"
@@ -2235,8 +2243,8 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
         }
         o += (u32)sigma[i];
     }
-    // demand 1 or 2: the bit-sliced kernel
-    if (d <= 2 && m > 0 && c_hi > c_lo && opts().ms_bits.load() != 0) {
+    // demand 1 to 3: the bit-sliced kernel
+    if (d <= 3 && m > 0 && c_hi > c_lo && opts().ms_bits.load() != 0) {
         std::vector<int> su(m), sv(m);
         for (int j = 0; j < m; ++j) {
             su[j] = K.u[j];
@@ -2245,7 +2253,7 @@ int ms_run(int32_t n, int32_t m, const bat_arc *arcs, const int32_t *sigma, cons
         return ms_bits_run(n, m, su.data(), sv.data(), K.sig, K.off, capt, wt, s, t, d, K.directed != 0, c_lo, c_hi,
                            R_hi, R_lo, count, src_only);
     }
-    if (src_only) return fail(BAT_EINVAL, "no bit-sliced kernel for this sweep (it needs demand 1 or 2 and arcs)");
+    if (src_only) return fail(BAT_EINVAL, "no bit-sliced kernel for this sweep (it needs demand 1 to 3 and arcs)");
     // slot 0's capacity nondecreasing in its state: the kernel's shortcuts
     // along slot 0 are exact
     K.warm = m > 0 ? 1u : 0u;

@@ -1,10 +1,11 @@
-"""Host side of the bit-sliced multi-state kernel (demand 1 or 2).
+"""Host side of the bit-sliced multi-state kernel (demands 1 to 3).
 
-For demand d <= 2 the library decides the maximum s-t flow word by word:
-flow >= 1 when t is reachable over the arcs of capacity >= 1, and flow >= 2
-when besides no single arc of capacity exactly 1 separates s from t there
-(max-flow min-cut: a cut of capacity 1 is one unit arc plus arcs of
-capacity 0).  The constants the host bakes into the kernel (the word
+For demand d <= 3 the library decides the maximum s-t flow word by word:
+flow >= 1 when t is reachable over the arcs of capacity >= 1, flow >= 2
+when besides no single arc of capacity exactly 1 separates s from t there,
+and flow >= 3 when no single arc of capacity 1 or 2 and no two arcs of
+capacity 1 do (max-flow min-cut: the cuts of capacity 1 and 2 besides
+arcs of capacity 0).  The constants the host bakes into the kernel (the word
 slots' state patterns, the mixed-radix split of a vector's index into word
 bits, uniform run steps and lane digits) are read back from the generated
 source and the kernel's steps are replayed here on the CPU, on every
@@ -78,19 +79,19 @@ def _replay(G, c_lo=None, c_hi=None):
     mask = lambda bits, x: FULL32 if (bits >> x) & 1 else 0  # noqa: E731
     count = 0
     for lane_run in range(rl_lo, rl_hi):
-        W, U = [0] * M, [0] * M
+        W, U, U2 = [0] * M, [0] * M, [0] * M
         rl = lane_run
         for j in range(M):
             if j < KW:
-                W[j], U[j] = G["WW1"][j], G["WU1"][j]
+                W[j], U[j], U2[j] = G["WW1"][j], G["WU1"][j], G["WU12"][j]
             elif j >= KW + KR:
                 x = rl % G["SIG"][j]
                 rl //= G["SIG"][j]
-                W[j], U[j] = mask(G["C1"][j], x), mask(G["CE1"][j], x)
+                W[j], U[j], U2[j] = mask(G["C1"][j], x), mask(G["CE1"][j], x), mask(G["CE12"][j], x)
         xr = [0] * M
         for step in range(RUN):
             for j in range(KW, KW + KR):
-                W[j], U[j] = mask(G["C1"][j], xr[j]), mask(G["CE1"][j], xr[j])
+                W[j], U[j], U2[j] = mask(G["C1"][j], xr[j]), mask(G["CE1"][j], xr[j]), mask(G["CE12"][j], xr[j])
             c0 = (lane_run * RUN + step) * B
             full = sum(1 << b for b in range(B) if c_lo <= c0 + b < c_hi) & G["FULL"]
             r0 = _closure(G, W, full, full, -1)
@@ -100,6 +101,20 @@ def _replay(G, c_lo=None, c_hi=None):
                     need = V & U[j] & r0[G["NU"][j]]
                     if G["CE1"][j] and need:
                         V &= (~need | _closure(G, W, need, need, j)[G["T"]]) & FULL32
+            if G["D"] == 3:
+                # one arc of capacity 1 or 2, then two arcs of capacity 1
+                for j in range(M):
+                    need = V & U2[j] & r0[G["NU"][j]]
+                    if G["CE12"][j] and need:
+                        V &= (~need | _closure(G, W, need, need, j)[G["T"]]) & FULL32
+                for j1 in range(M):
+                    for j2 in range(j1 + 1, M):
+                        if not (G["CE1"][j1] and G["CE1"][j2]):
+                            continue
+                        need = V & U[j1] & U[j2] & (r0[G["NU"][j1]] | r0[G["NU"][j2]])
+                        if need:
+                            Wp = [0 if j in (j1, j2) else W[j] for j in range(M)]
+                            V &= (~need | _closure(G, Wp, need, need, -1)[G["T"]]) & FULL32
             count += bin(V).count("1")
             for j in range(KW, KW + KR):
                 xr[j] += 1
@@ -126,7 +141,7 @@ def _random_net(seed, lo_states=1, hi_states=4):
 @pytest.mark.parametrize("run", [0, 3, 9])
 def test_bit_sliced_steps_count_like_the_oracle(seed, run):
     """Random graphs, 1-4 states with capacities 0-2 in any order, both arc
-    readings, demands 1 and 2, runs of the default length and of at most 3
+    readings, demands 1 to 3, runs of the default length and of at most 3
     and 9 steps (option BAT_MS_RUN, which moves slots from the lanes to the
     uniform run)."""
     B = _B()
@@ -136,7 +151,7 @@ def test_bit_sliced_steps_count_like_the_oracle(seed, run):
     try:
         B.bat_set_option("BAT_MS_RUN", run)
         for directed in (False, True):
-            for d in (1, 2):
+            for d in (1, 2, 3):
                 G = _consts(B.bat_ms_jit_source(n, arcs, sigma, cap, 0, n - 1, d, directed=directed))
                 assert G["D"] == d and G["DIR"] == directed
                 if run:
@@ -168,7 +183,7 @@ def test_bit_sliced_ranges_count_like_the_oracle(seed):
         for run in (1, 3, 9):
             B.bat_set_option("BAT_MS_RUN", run)
             for directed in (False, True):
-                for d in (1, 2):
+                for d in (1, 2, 3):
                     for c_lo, c_hi in cases:
                         G = _consts(B.bat_ms_jit_source(n, arcs, sigma, cap, 0, n - 1, d, directed=directed,
                                                         c_lo=c_lo, c_hi=c_hi))
@@ -187,7 +202,7 @@ def test_word_patterns_and_split():
     B = _B()
     arcs = [(0, 1), (1, 2), (0, 2), (2, 3), (1, 3)]
     sigma = [2, 4, 3, 5, 2]
-    cap = [[0, 1], [2, 0, 1, 1], [1, 2, 0], [0, 0, 1, 2, 3], [3, 1]]
+    cap = [[0, 1], [2, 0, 1, 1], [2, 2, 0], [0, 0, 1, 2, 3], [3, 1]]
     G = _consts(B.bat_ms_jit_source(4, arcs, sigma, cap, 0, 3, 2))
     # whole sweeps reorder the arcs by breadth-first distance from s: read
     # each slot's states back through its state count and capacity masks
@@ -204,25 +219,29 @@ def test_word_patterns_and_split():
         assert G["SIG"][j] == sigma[i]
         assert G["C1"][j] == sum(1 << x for x, c in enumerate(cap[i]) if c >= 1)
         assert G["CE1"][j] == sum(1 << x for x, c in enumerate(cap[i]) if c == 1)
+        assert G["CE12"][j] == sum(1 << x for x, c in enumerate(cap[i]) if c in (1, 2))
+        assert (G["UPAIR"] >> j) & 1 == (1 in cap[i])
         if j < G["KW"]:
             for b in range(B_):
                 x = (b // stride) % sigma[i]
                 assert (G["WW1"][j] >> b) & 1 == (cap[i][x] >= 1)
                 assert (G["WU1"][j] >> b) & 1 == (cap[i][x] == 1)
+                assert (G["WU12"][j] >> b) & 1 == (cap[i][x] in (1, 2))
             stride *= sigma[i]
         else:
-            assert G["WW1"][j] == G["WU1"][j] == 0
+            assert G["WW1"][j] == G["WU1"][j] == G["WU12"][j] == 0
 
 
-def test_only_demand_one_or_two():
+def test_only_demands_up_to_three():
     B = _B()
     arcs = [(0, 1), (1, 2)]
     with pytest.raises(B.BatError):
-        B.bat_ms_jit_source(3, arcs, [3, 3], None, 0, 2, 3)
+        B.bat_ms_jit_source(3, arcs, [3, 3], None, 0, 2, 4)
     with pytest.raises(B.BatError):
         B.bat_ms_jit_source(3, [], [], None, 0, 2, 1)
     src = B.bat_ms_jit_source(3, arcs, [3, 3], None, 0, 2, 1)
     assert "bat_ms_bits" in src and "MsCut" in src
+    assert "D = 3u" in B.bat_ms_jit_source(3, arcs, [3, 3], None, 0, 2, 3)
 
 
 @pytest.mark.skipif(shutil.which("hipcc") is None and not __import__("os").path.exists("/opt/rocm/bin/hipcc"),
