@@ -313,14 +313,15 @@ int bat_reliability_noalloc(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs
  * calling thread's stream; the same workspace rules as bat_reliability.
  *
  * bat_ms_reliability sweeps every vector (in any arc order it likes: R and
- * the count are sums).  With demand 1 or 2 both entry points decide the flow test
- * bit-sliced, up to 32 vectors per word, in a kernel compiled at run time
- * for the graph, its states and capacities (hiprtc, cached like the other
- * graph-specialised kernels; probabilities are run-time data): by
- * max-flow min-cut the flow reaches 1 when t is reachable from s over the
- * arcs of capacity >= 1, and 2 when besides no single arc of capacity
- * exactly 1 separates s from t there.  Other demands run the
- * augmenting-path kernel.  bat_ms_reliability_range sweeps indices
+ * the count are sums).  With demand 1 to 3 both entry points decide the
+ * flow test bit-sliced, up to 32 vectors per word, in a kernel compiled at
+ * run time for the graph, its states and capacities (hiprtc, cached like
+ * the other graph-specialised kernels; probabilities are run-time data):
+ * by max-flow min-cut the flow reaches 1 when t is reachable from s over
+ * the arcs of capacity >= 1, 2 when besides no single arc of capacity
+ * exactly 1 separates s from t there, and 3 when no single arc of
+ * capacity 1 or 2 and no two arcs of capacity 1 do.  Higher demands run
+ * the augmenting-path kernel.  bat_ms_reliability_range sweeps indices
  * [c_lo, c_hi) in the order above and returns the partial sum as a
  * double-double (R_hi + R_lo) and its count.
  */
@@ -369,8 +370,8 @@ int bat_ms_reliability_range(int32_t n_nodes, int32_t n_arcs, const bat_arc *arc
  *                      multi-state augmenting-path sweep decides, and the
  *                      most words each lane of the bit-sliced sweep
  *                      (demand <= 2) steps through (0 = automatic)
- *   "BAT_MS_BITS"      1 (default) = whole multi-state sweeps with demand 1
- *                      or 2 run the bit-sliced kernel; 0 = always the
+ *   "BAT_MS_BITS"      1 (default) = multi-state sweeps with demand 1 to 3
+ *                      run the bit-sliced kernel; 0 = always the
  *                      augmenting-path kernel
  *   "BAT_WINDOW_TEST"  1 (default) = the graph-specialised sweeps (R, and
  *                      R with the gradient) test each window of 2048 iterations once, with all
@@ -529,7 +530,7 @@ int bat_jit_source(int32_t n_nodes, int32_t n_arcs, const bat_arc *arcs, int32_t
  * The source text of the graph-specialised multi-state kernel that
  * bat_ms_reliability (c_lo = c_hi = 0) or bat_ms_reliability_range over
  * [c_lo, c_hi) compiles for this graph, these states and capacities
- * (capacity NULL: state k has capacity k) and demand 1 or 2 (BAT_EINVAL
+ * (capacity NULL: state k has capacity k) and demand 1 to 3 (BAT_EINVAL
  * otherwise, with no arcs, or for an empty or invalid range).  Same
  * conventions as bat_jit_source; the text does not depend on the
  * probabilities.

@@ -398,7 +398,7 @@ def bat_jit_source(n_nodes: int, arcs, s: int, t: int, grad: bool = False, perm:
 def bat_ms_jit_source(n_nodes: int, arcs, n_states, capacity, s: int, t: int, demand: int,
                       directed: bool = False, c_lo: int = 0, c_hi: int = 0) -> str:
     """The hiprtc source of the bit-sliced multi-state kernel that a sweep
-    with demand 1 or 2 compiles (diagnostics): the whole space when
+    with demand 1 to 3 compiles (diagnostics): the whole space when
     c_lo = c_hi = 0, else the range [c_lo, c_hi)."""
     w = [[1.0] * int(k) for k in n_states]
     a, m, sg, cf, _ = _ms_args(arcs, n_states, capacity, w)
