@@ -484,13 +484,24 @@ def main():
         B.bat_set_option("BAT_MS_BITS", 0)
         Rf, cf = B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, msn.d)
         fk = B.bat_last_launch().kernel_ms
+        # and the same graph at demand 3, on both kernels
+        R3f, c3f = B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, 3)
+        fk3 = B.bat_last_launch().kernel_ms
         B.bat_set_option("BAT_MS_BITS", old_bits)
         assert cf == cm
+        B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, 3)
+        k3 = []
+        for _ in range(3):
+            R3, c3_ = B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, 3)
+            k3.append(B.bat_last_launch().kernel_ms)
+        assert c3_ == c3f
         ms_out = {"workload": f"random n={msn.n} m={msn.m} (seed 220909711/5), 3 capacity levels per arc, "
                               f"demand {msn.d}, {msn.space} state vectors",
                   "R": Rm, "count": cm, "kernel_ms": min(mks), "wall_ms": mw * 1e3,
                   "value": msn.space / (min(mks) / 1e3) / 1e9, "unit": "Gvec/s",
-                  "bit_sliced": bits, "flow_kernel_ms": fk, "flow_R_rel_diff": abs(Rf - Rm) / Rm if Rm else 0.0}
+                  "bit_sliced": bits, "flow_kernel_ms": fk, "flow_R_rel_diff": abs(Rf - Rm) / Rm if Rm else 0.0,
+                  "demand3": {"R": R3, "count": c3_, "kernel_ms": min(k3), "flow_kernel_ms": fk3,
+                              "flow_R_rel_diff": abs(R3f - R3) / R3 if R3 else 0.0}}
         out["multistate"] = ms_out
 
     cpu = None
