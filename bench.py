@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--cpu-sample-log2", type=int, default=30,
                     help="log2 of the state vectors in the oracle's timed sample")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--ms-demand", type=int, default=0,
+                    help="with --multistate-only: this demand instead of the workload's")
     ap.add_argument("--multistate-only", action="store_true",
                     help="only time the multi-state workload's sweep (for profiling runs)")
     ap.add_argument("--valu-peak-only", action="store_true",
@@ -272,10 +274,12 @@ def main():
         import bat_workloads as W
         import paper_2209_09711_amd as B
         msn = W.config_ms()
+        dem = a.ms_demand if a.ms_demand > 0 else msn.d
+
         def calls(k):
             ks = []
             for _ in range(k):
-                R, c = B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, msn.d)
+                R, c = B.bat_ms_reliability(msn.n, msn.arcs, msn.sigma, msn.cap, msn.w, msn.s, msn.t, dem)
                 ks.append(B.bat_last_launch().kernel_ms)
             return R, c, ks
         R, c, _ = calls(1)
@@ -287,7 +291,7 @@ def main():
         B.bat_set_option("BAT_MS_BITS", 0)
         Rf, cf, kf = calls(2)
         B.bat_set_option("BAT_MS_BITS", old)
-        print(json.dumps({"workload": msn.name, "state_vectors": msn.space, "R": R, "count": c,
+        print(json.dumps({"workload": msn.name, "demand": dem, "state_vectors": msn.space, "R": R, "count": c,
                           "kernel_ms_all": ks, "bit_sliced": bits, "first_call_jit_ms": first_jit_ms,
                           "flow_kernel_ms_all": kf, "flow_R": Rf, "flow_count": cf}), flush=True)
         return
